@@ -1,0 +1,160 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) isothermal lattice Boltzmann library.
+ *
+ * Method: Negro, Busuioc, Ambrus, Gonnella, Lamura, Sofonea, "Comparison
+ * between isothermal collision-streaming and finite-difference lattice
+ * Boltzmann models", arXiv:1904.02471.
+ *
+ *   collision-streaming (CS) D2Q9:  Section 2, CS evolution equation
+ *       f_k(x + v_k dt, t + dt) - f_k(x, t) = -(dt / tau) (f_k - f_eq_k)
+ *   finite-difference (FD) Gauss-Hermite D2Q(Q*Q), Q = 3..6:  Section 2, BGK
+ *       equation d_t f_k + v_k . grad f_k = -(f_k - f_eq_k) / tau advanced by
+ *       third-order TVD Runge-Kutta with WENO-5 advection
+ *   equilibrium: Hermite expansion of the Maxwellian to total order N
+ *       (Section 1; second-order form in Section 2)
+ *   moments: rho = sum_k f_k, rho u = sum_k f_k v_k (Section 2)
+ *
+ * Conventions shared by every call
+ *   - Fields are row-major [Ny][Nx] float64 host arrays, x fastest; the node
+ *     (i, j) sits at (i ds, j ds).  Distributions are [K][Ny][Nx].
+ *   - CS D2Q9 population order: 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW,
+ *     7 SW, 8 SE; v_k = e_k ds/dt, sound speed c_s = (ds/dt)/sqrt(3); tau
+ *     is in the time unit of dt; N must be 2.
+ *   - FD population order k = j*Q + i with v_k = (xi_i, xi_j), xi the
+ *     ascending roots of the Hermite polynomial He_Q; units c_s = 1
+ *     (T = m = 1, Section 4.1); ds is the grid spacing; 1 <= N <= Q-1.
+ *   - All pointers are caller-owned host pointers unless stated; the library
+ *     never frees caller memory and never keeps a caller pointer after a call
+ *     returns.
+ *   - Calls on one handle are not thread-safe; distinct handles are
+ *     independent.  lb_step is asynchronous on the handle's stream; every
+ *     call that returns host data synchronises that stream first.
+ *   - Return value: LB_OK (0) or a negative LB_E* code; lb_create returns NULL
+ *     on error and lb_last_error() (per thread) gives the code.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* models (low byte of the model_flags argument) */
+enum lb_model {
+    LB_CS_D2Q9 = 0,
+    LB_FD_D2Q9 = 1,
+    LB_FD_D2Q16 = 2,
+    LB_FD_D2Q25 = 3,
+    LB_FD_D2Q36 = 4
+};
+
+/* storage precision (bits 8-9).  The stored quantity is always the shifted
+ * g_k = f_k - w_k rho0 (rho0 = mean initial density); arithmetic is FP32 for
+ * LB_FP32 and LB_FP16_SHIFTED, FP64 for LB_FP64. */
+enum lb_precision {
+    LB_FP32 = 0,
+    LB_FP16_SHIFTED = 1 << 8,
+    LB_FP64 = 2 << 8
+};
+#define LB_PRECISION_MASK (3 << 8)
+
+enum lb_status {
+    LB_OK = 0,
+    LB_EINVAL = -1,  /* bad model, size, order, pointer or argument */
+    LB_ECFL = -2,    /* FD: max |v_k,alpha| dt / ds > 1 (Section 4.1 CFL bound) */
+    LB_ESTIFF = -3,  /* FD: dt > tau, explicit collision would be stiff (Section 4.1) */
+    LB_ENOMEM = -4,  /* device allocation failed */
+    LB_EDEVICE = -5, /* HIP runtime error */
+    LB_ENAN = -6,    /* non-finite diagnostics */
+    LB_EBUSY = -7,   /* server: budget or slots exhausted */
+    LB_ESTATE = -8   /* call out of order (e.g. step before init) */
+};
+
+typedef struct lb_sim lb_sim;
+
+/* Create a simulation of Nx x Ny nodes (periodic in x and y).
+ *   model_flags: lb_model | lb_precision.
+ *   tau, dt, ds: relaxation time, time step, grid spacing (see conventions).
+ *   N: order of the Hermite expansion of the equilibrium.
+ * Validation: Nx, Ny >= 1 (FD: >= 3); CS needs N == 2 and tau > dt/2
+ * (positive viscosity nu = c_s^2 (tau - dt/2), Section 2); FD needs
+ * 1 <= N <= Q-1, the CFL bound and dt <= tau (Section 4.1).
+ * Allocates all device memory (2 state buffers for CS, 3 for FD) on the
+ * current HIP device.  Returns NULL on error (see lb_last_error). */
+lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N);
+
+/* Release all device memory of the handle.  NULL is ignored. */
+void lb_destroy(lb_sim *sim);
+
+/* Code of the last failed call on this thread (LB_OK if none). */
+int lb_last_error(void);
+
+/* Static description of a status code. */
+const char *lb_strerror(int code);
+
+/* Velocity set of a model: writes K values to vx, vy, w (each may be NULL)
+ * and the sound speed to *cs (may be NULL); for CS uses ds and dt, for FD
+ * ignores them.  Returns K (> 0) or LB_EINVAL. */
+int lb_model_info(int model, double ds, double dt, double *vx, double *vy, double *w, double *cs);
+
+/* Fixed-value ends in x: the nodes beyond x = 0 and x = Nx-1 hold the
+ * equilibrium at (rho_left, u = 0) and (rho_right, u = 0); y stays periodic.
+ * Must be called before lb_init / lb_set_state.  Densities must be > 0. */
+int lb_set_bc_x(lb_sim *sim, double rho_left, double rho_right);
+
+/* FD only: tolerance eps of the WENO-5 nonlinear weights (default 1e-6). */
+int lb_set_weno_eps(lb_sim *sim, double eps);
+
+/* f := f_eq(rho, u) at every node (rho > 0).  Sets rho0 to the mean of rho
+ * and resets the step counter.  Arrays [Ny][Nx]. */
+int lb_init(lb_sim *sim, const double *rho, const double *ux, const double *uy);
+
+/* Advance nsteps >= 0 time steps (CS: one fused pull stream-collide launch
+ * per step; FD: three RK stage launches per step).  Asynchronous. */
+int lb_step(lb_sim *sim, int nsteps);
+
+/* Density and velocity of the current state, [Ny][Nx] each (any may be NULL). */
+int lb_moments(lb_sim *sim, double *rho, double *ux, double *uy);
+
+/* Velocity pattern for the amplitude diagnostic, as products of 1-D
+ * factors: phi_x(i, j) = ax[i] ay[j], phi_y(i, j) = bx[i] by[j]
+ * (ax, bx: Nx values; ay, by: Ny values).  All NULL clears the pattern. */
+int lb_set_probe(lb_sim *sim, const double *ax, const double *ay, const double *bx, const double *by);
+
+/* Diagnostics of the current state, accumulated in FP64 on the device in a
+ * fixed order (deterministic):
+ *   out[0] M  = sum rho          out[1], out[2] P = sum rho u
+ *   out[3] E  = sum rho |u|^2/2  out[4] A = sum u.phi / sum phi.phi (0 without a probe)
+ * Returns LB_ENAN when a result is not finite. */
+int lb_reduce(lb_sim *sim, double out[5]);
+
+/* Run nsteps steps and record the diagnostics every `every` steps (at steps
+ * 0, every, 2 every, ... <= nsteps) into series[(nsteps / every + 1) * 5],
+ * fused into the step kernels where possible.  Synchronises. */
+int lb_run_sampled(lb_sim *sim, int nsteps, int every, double *series);
+
+/* Canonical (pre-collision) distribution f_k(x, t), [K][Ny][Nx] float64. */
+int lb_get_state(lb_sim *sim, double *f);
+int lb_set_state(lb_sim *sim, const double *f);
+
+/* Number of steps taken since lb_init / lb_set_state. */
+long long lb_steps_done(const lb_sim *sim);
+
+/* Launch on a caller-owned HIP stream (hipStream_t passed as void*; NULL
+ * means the library's own stream).  The caller keeps the stream alive. */
+int lb_set_stream(lb_sim *sim, void *hip_stream);
+
+/* Block until the handle's stream is idle. */
+int lb_synchronize(lb_sim *sim);
+
+/* Device bytes held by the handle. */
+size_t lb_device_bytes(const lb_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

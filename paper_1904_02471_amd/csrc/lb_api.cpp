@@ -1,0 +1,667 @@
+// lb_api.cpp -- the C ABI of include/lb.h: handle, parameter validation,
+// device buffers, launch sequencing and host/device transfers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "lb.h"
+#include "lb_internal.h"
+#include "lb_model.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local int g_last_error = LB_OK;
+
+int fail(int code)
+{
+    g_last_error = code;
+    return code;
+}
+
+enum Prec { P32 = 0, P16 = 1, P64 = 2 };
+
+}  // namespace
+
+struct lb_sim {
+    int model = 0;
+    Prec prec = P32;
+    bool cs = true;
+    int Nx = 0, Ny = 0, K = 0, Q = 0, N = 0;
+    double tau = 0, dt = 0, ds = 0;
+    ModelInfo mi{};
+    double rho0 = 1.0;
+    bool fixed = false;
+    double rho_l = 1.0, rho_r = 1.0;
+    double eps = 1e-6;
+    bool ready = false;
+    long long steps = 0;
+    int cur = 0;  // CS: buffer holding the current state
+    int pitch = 0, xoff = 0;
+    long long plane = 0;
+    size_t esize = 4;
+    int nbuf = 0;
+    void *buf[3] = {nullptr, nullptr, nullptr};
+    size_t buf_bytes = 0;
+    hipStream_t stream = nullptr, own_stream = nullptr;
+    double *d_partial = nullptr;  // per-block diagnostics partials
+    int partial_blocks = 0;
+    double *d_out = nullptr;      // kDiag doubles
+    bool probe = false;
+    double probe_den = 0.0;
+    double *d_probe64 = nullptr;  // ax | ay | bx | by
+    float *d_probe32 = nullptr;
+};
+
+namespace {
+
+size_t elem_size(Prec p) { return p == P16 ? 2 : (p == P64 ? 8 : 4); }
+
+template <typename CT>
+Params<CT> make_params(const lb_sim *s)
+{
+    Params<CT> p{};
+    p.Nx = s->Nx;
+    p.Ny = s->Ny;
+    p.pitch = s->pitch;
+    p.xoff = s->xoff;
+    p.plane = s->plane;
+    p.K = s->K;
+    p.Q = s->Q;
+    p.N = s->N;
+    p.fixed_x = s->fixed ? 1 : 0;
+    p.rho0 = (CT)s->rho0;
+    p.cs = (CT)s->mi.cs;
+    p.omega = (CT)(s->dt / s->tau);
+    p.dt = (CT)s->dt;
+    p.inv_ds = (CT)(1.0 / s->ds);
+    p.inv_tau = (CT)(1.0 / s->tau);
+    p.eps = (CT)s->eps;
+    for (int k = 0; k < s->K; ++k) {
+        p.w[k] = (CT)s->mi.w[k];
+        p.vx[k] = (CT)s->mi.vx[k];
+        p.vy[k] = (CT)s->mi.vy[k];
+        p.ki[k] = s->mi.ki[k];
+        p.kj[k] = s->mi.kj[k];
+        // the end equilibria at u = 0 are w_k rho_end exactly, for every order
+        p.ghost_l[k] = (CT)(s->mi.w[k] * (s->rho_l - s->rho0));
+        p.ghost_r[k] = (CT)(s->mi.w[k] * (s->rho_r - s->rho0));
+    }
+    for (int i = 0; i < s->Q; ++i)
+        for (int n = 0; n <= kMaxN; ++n) p.hc[i][n] = (CT)s->mi.hc[i][n];
+    return p;
+}
+
+void free_buffers(lb_sim *s)
+{
+    for (int i = 0; i < 3; ++i) {
+        if (s->buf[i]) (void)hipFree(s->buf[i]);
+        s->buf[i] = nullptr;
+    }
+}
+
+int alloc_buffers(lb_sim *s)
+{
+    free_buffers(s);
+    s->xoff = (s->cs && s->fixed) ? 1 : 0;
+    s->pitch = s->Nx + 2 * s->xoff;
+    s->plane = (long long)s->pitch * s->Ny;
+    s->buf_bytes = (size_t)s->K * (size_t)s->plane * s->esize;
+    for (int i = 0; i < s->nbuf; ++i) {
+        if (hipMalloc(&s->buf[i], s->buf_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            free_buffers(s);
+            return LB_ENOMEM;
+        }
+        if (hipMemsetAsync(s->buf[i], 0, s->buf_bytes, s->stream) != hipSuccess) return LB_EDEVICE;
+    }
+    return LB_OK;
+}
+
+template <typename T>
+T *bufp(lb_sim *s, int i)
+{
+    return static_cast<T *>(s->buf[i]);
+}
+
+// Dispatch on the storage type.
+template <typename F>
+hipError_t with_type(lb_sim *s, F &&f)
+{
+    switch (s->prec) {
+    case P16: return f((__half *)nullptr);
+    case P64: return f((double *)nullptr);
+    default: return f((float *)nullptr);
+    }
+}
+
+int dev_status(hipError_t e) { return e == hipSuccess ? LB_OK : (e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE); }
+
+// Current canonical-state buffer.
+int state_index(const lb_sim *s) { return s->cs ? s->cur : 0; }
+
+// Advance one step; diag non-null fuses the diagnostics of the input state.
+template <typename T>
+hipError_t step_once(lb_sim *s, bool with_diag)
+{
+    using CT = typename Arith<T>::type;
+    const Params<CT> p = make_params<CT>(s);
+    DiagArgs<CT> d{};
+    d.partial = s->d_partial;
+    if (s->probe) {
+        if constexpr (sizeof(CT) == 8) {
+            d.ax = s->d_probe64;
+            d.ay = s->d_probe64 + s->Nx;
+            d.bx = s->d_probe64 + s->Nx + s->Ny;
+            d.by = s->d_probe64 + 2 * s->Nx + s->Ny;
+        } else {
+            d.ax = s->d_probe32;
+            d.ay = s->d_probe32 + s->Nx;
+            d.bx = s->d_probe32 + s->Nx + s->Ny;
+            d.by = s->d_probe32 + 2 * s->Nx + s->Ny;
+        }
+    }
+    const DiagArgs<CT> *dp = with_diag ? &d : nullptr;
+    hipError_t e;
+    if (s->cs) {
+        e = launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, dp, s->stream);
+        s->cur ^= 1;
+    } else {
+        T *g = bufp<T>(s, 0), *a = bufp<T>(s, 1), *b = bufp<T>(s, 2);
+        e = launch_fd_stage<T>(g, nullptr, a, 1, p, dp, s->stream);
+        if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream);
+        if (e == hipSuccess) e = launch_fd_stage<T>(b, g, g, 3, p, nullptr, s->stream);
+    }
+    if (e == hipSuccess) ++s->steps;
+    return e;
+}
+
+int diag_blocks_fused(const lb_sim *s) { return s->cs ? cs_diag_blocks(s->Nx, s->Ny) : fd_diag_blocks(s->Nx, s->Ny); }
+
+// Convert the device sums (sum drho, sum jx, sum jy, sum rho u^2/2, sum u.phi)
+// into {M, Px, Py, E, A}; `vscale` converts the kernel's velocity unit.
+void finish_diag(const lb_sim *s, const double *raw, double vscale, double *out)
+{
+    const double nodes = (double)s->Nx * (double)s->Ny;
+    out[0] = s->rho0 * nodes + raw[0];
+    out[1] = raw[1] * vscale;
+    out[2] = raw[2] * vscale;
+    out[3] = raw[3] * vscale * vscale;
+    out[4] = s->probe ? raw[4] * vscale / s->probe_den : 0.0;
+}
+
+template <typename T>
+hipError_t reduce_into(lb_sim *s, double *d_dst)
+{
+    const Params<double> p = make_params<double>(s);
+    DiagArgs<double> d{};
+    d.partial = s->d_partial;
+    if (s->probe) {
+        d.ax = s->d_probe64;
+        d.ay = s->d_probe64 + s->Nx;
+        d.bx = s->d_probe64 + s->Nx + s->Ny;
+        d.by = s->d_probe64 + 2 * s->Nx + s->Ny;
+    }
+    hipError_t e = launch_reduce<T>(bufp<T>(s, state_index(s)), s->cs, p, d, s->stream);
+    if (e == hipSuccess) e = launch_diag_finalize(s->d_partial, reduce_diag_blocks(s->Nx, s->Ny), d_dst, s->stream);
+    return e;
+}
+
+bool all_finite(const double *v, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_last_error(void) { return g_last_error; }
+
+const char *lb_strerror(int code)
+{
+    switch (code) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ECFL: return "time step violates the CFL bound max|v| dt/ds <= 1";
+    case LB_ESTIFF: return "FD time step larger than the relaxation time";
+    case LB_ENOMEM: return "device memory exhausted";
+    case LB_EDEVICE: return "HIP runtime error";
+    case LB_ENAN: return "non-finite result";
+    case LB_EBUSY: return "server budget or slots exhausted";
+    case LB_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+int lb_model_info(int model, double ds, double dt, double *vx, double *vy, double *w, double *cs)
+{
+    ModelInfo mi{};
+    if (!model_info(model, ds, dt, &mi)) return fail(LB_EINVAL);
+    for (int k = 0; k < mi.K; ++k) {
+        if (vx) vx[k] = mi.vx[k];
+        if (vy) vy[k] = mi.vy[k];
+        if (w) w[k] = mi.w[k];
+    }
+    if (cs) *cs = mi.cs;
+    return mi.K;
+}
+
+lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N)
+{
+    const int model = model_flags & 0xff;
+    const int precbits = model_flags & LB_PRECISION_MASK;
+    if ((model_flags & ~(0xff | LB_PRECISION_MASK)) != 0 || precbits == (3 << 8)) {
+        fail(LB_EINVAL);
+        return nullptr;
+    }
+    ModelInfo mi{};
+    if (!(tau > 0) || !(dt > 0) || !(ds > 0) || !std::isfinite(tau) || !std::isfinite(dt) || !std::isfinite(ds) ||
+        Nx < 1 || Ny < 1 || (long long)Nx * Ny > (1LL << 30) || !model_info(model, ds, dt, &mi)) {
+        fail(LB_EINVAL);
+        return nullptr;
+    }
+    const bool cs = model == LB_CS_D2Q9;
+    if (cs) {
+        // positive viscosity nu = c_s^2 (tau - dt/2) (Section 2)
+        if (N != 2 || !(tau > 0.5 * dt)) {
+            fail(LB_EINVAL);
+            return nullptr;
+        }
+    } else {
+        if (N < 1 || N > mi.Q - 1) {
+            fail(LB_EINVAL);
+            return nullptr;
+        }
+        // CFL = max |v_k,alpha| dt / ds <= 1 and dt < tau (Section 4.1);
+        // dt == tau is accepted, as in the shear-wave runs of Section 4.2
+        const double vmax = mi.xi[mi.Q - 1];
+        if (vmax * dt / ds > 1.0 + 1e-12) {
+            fail(LB_ECFL);
+            return nullptr;
+        }
+        if (dt > tau * (1.0 + 1e-12)) {
+            fail(LB_ESTIFF);
+            return nullptr;
+        }
+    }
+    lb_sim *s = new (std::nothrow) lb_sim();
+    if (!s) {
+        fail(LB_ENOMEM);
+        return nullptr;
+    }
+    s->model = model;
+    s->prec = precbits == LB_FP16_SHIFTED ? P16 : (precbits == LB_FP64 ? P64 : P32);
+    s->cs = cs;
+    s->Nx = Nx;
+    s->Ny = Ny;
+    s->K = mi.K;
+    s->Q = mi.Q;
+    s->N = N;
+    s->tau = tau;
+    s->dt = dt;
+    s->ds = ds;
+    s->mi = mi;
+    s->esize = elem_size(s->prec);
+    s->nbuf = cs ? 2 : 3;
+    if (hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        fail(LB_EDEVICE);
+        return nullptr;
+    }
+    s->stream = s->own_stream;
+    int rc = alloc_buffers(s);
+    if (rc == LB_OK) {
+        int blocks = cs_diag_blocks(Nx, Ny);
+        blocks = std::max(blocks, fd_diag_blocks(Nx, Ny));
+        blocks = std::max(blocks, reduce_diag_blocks(Nx, Ny));
+        s->partial_blocks = blocks;
+        if (hipMalloc(&s->d_partial, sizeof(double) * kDiag * (size_t)blocks) != hipSuccess ||
+            hipMalloc(&s->d_out, sizeof(double) * kDiag) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = LB_ENOMEM;
+        }
+    }
+    if (rc != LB_OK) {
+        lb_destroy(s);
+        fail(rc);
+        return nullptr;
+    }
+    g_last_error = LB_OK;
+    return s;
+}
+
+void lb_destroy(lb_sim *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_buffers(s);
+    if (s->d_partial) (void)hipFree(s->d_partial);
+    if (s->d_out) (void)hipFree(s->d_out);
+    if (s->d_probe64) (void)hipFree(s->d_probe64);
+    if (s->d_probe32) (void)hipFree(s->d_probe32);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    delete s;
+}
+
+int lb_set_bc_x(lb_sim *s, double rho_left, double rho_right)
+{
+    if (!s || !(rho_left > 0) || !(rho_right > 0) || !std::isfinite(rho_left) || !std::isfinite(rho_right))
+        return fail(LB_EINVAL);
+    if (s->ready) return fail(LB_ESTATE);
+    const bool relayout = s->cs && !s->fixed;
+    s->fixed = true;
+    s->rho_l = rho_left;
+    s->rho_r = rho_right;
+    if (relayout) {
+        int rc = alloc_buffers(s);
+        if (rc != LB_OK) return fail(rc);
+    }
+    return LB_OK;
+}
+
+int lb_set_weno_eps(lb_sim *s, double eps)
+{
+    if (!s || !(eps > 0) || !std::isfinite(eps)) return fail(LB_EINVAL);
+    if (s->cs) return fail(LB_EINVAL);
+    s->eps = eps;
+    return LB_OK;
+}
+
+int lb_set_stream(lb_sim *s, void *hip_stream)
+{
+    if (!s) return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    s->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : s->own_stream;
+    return LB_OK;
+}
+
+int lb_synchronize(lb_sim *s)
+{
+    if (!s) return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    return LB_OK;
+}
+
+long long lb_steps_done(const lb_sim *s) { return s ? s->steps : -1; }
+
+size_t lb_device_bytes(const lb_sim *s)
+{
+    if (!s) return 0;
+    return s->nbuf * s->buf_bytes + sizeof(double) * kDiag * ((size_t)s->partial_blocks + 1) +
+           (s->d_probe64 ? 2 * (s->Nx + s->Ny) * (sizeof(double) + sizeof(float)) : 0);
+}
+
+// Upload fields / state through a temporary device buffer.
+static int upload(lb_sim *s, const double *h, size_t n, double **d)
+{
+    *d = nullptr;
+    if (hipMalloc(d, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return LB_ENOMEM;
+    }
+    if (hipMemcpyAsync(*d, h, n * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess) return LB_EDEVICE;
+    return LB_OK;
+}
+
+static int ghosts_and(lb_sim *s)
+{
+    if (!(s->cs && s->fixed)) return LB_OK;
+    const Params<double> p = make_params<double>(s);
+    for (int i = 0; i < s->nbuf; ++i) {
+        hipError_t e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return launch_fill_ghosts<T>(bufp<T>(s, i), p, s->stream);
+        });
+        if (e != hipSuccess) return dev_status(e);
+    }
+    return LB_OK;
+}
+
+int lb_init(lb_sim *s, const double *rho, const double *ux, const double *uy)
+{
+    if (!s || !rho || !ux || !uy) return fail(LB_EINVAL);
+    const size_t n = (size_t)s->Nx * s->Ny;
+    double mean = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        if (!(rho[i] > 0) || !std::isfinite(rho[i]) || !std::isfinite(ux[i]) || !std::isfinite(uy[i]))
+            return fail(LB_EINVAL);
+        mean += rho[i];
+    }
+    s->rho0 = mean / (double)n;
+    s->cur = 0;
+    int rc = ghosts_and(s);
+    if (rc != LB_OK) return fail(rc);
+    std::vector<double> host(3 * n);
+    std::memcpy(host.data(), rho, n * sizeof(double));
+    std::memcpy(host.data() + n, ux, n * sizeof(double));
+    std::memcpy(host.data() + 2 * n, uy, n * sizeof(double));
+    double *d = nullptr;
+    rc = upload(s, host.data(), 3 * n, &d);
+    if (rc == LB_OK) {
+        const Params<double> p = make_params<double>(s);
+        hipError_t e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return launch_init<T>(bufp<T>(s, 0), d, d + n, d + 2 * n, s->cs, p, s->stream);
+        });
+        rc = dev_status(e);
+        if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+    }
+    if (d) (void)hipFree(d);
+    if (rc != LB_OK) return fail(rc);
+    s->steps = 0;
+    s->ready = true;
+    return LB_OK;
+}
+
+int lb_set_state(lb_sim *s, const double *f)
+{
+    if (!s || !f) return fail(LB_EINVAL);
+    const size_t nodes = (size_t)s->Nx * s->Ny, n = nodes * s->K;
+    double mass = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        if (!std::isfinite(f[i])) return fail(LB_EINVAL);
+        mass += f[i];
+    }
+    s->rho0 = mass / (double)nodes;
+    s->cur = 0;
+    int rc = ghosts_and(s);
+    if (rc != LB_OK) return fail(rc);
+    double *d = nullptr;
+    rc = upload(s, f, n, &d);
+    if (rc == LB_OK) {
+        const Params<double> p = make_params<double>(s);
+        hipError_t e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return launch_set_state<T>(bufp<T>(s, 0), d, s->cs, p, s->stream);
+        });
+        rc = dev_status(e);
+        if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+    }
+    if (d) (void)hipFree(d);
+    if (rc != LB_OK) return fail(rc);
+    s->steps = 0;
+    s->ready = true;
+    return LB_OK;
+}
+
+int lb_get_state(lb_sim *s, double *f)
+{
+    if (!s || !f) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    const size_t n = (size_t)s->Nx * s->Ny * s->K;
+    double *d = nullptr;
+    if (hipMalloc(&d, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LB_ENOMEM);
+    }
+    const Params<double> p = make_params<double>(s);
+    hipError_t e = with_type(s, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_get_state<T>(bufp<T>(s, state_index(s)), d, s->cs, p, s->stream);
+    });
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(dev_status(e));
+    return LB_OK;
+}
+
+int lb_moments(lb_sim *s, double *rho, double *ux, double *uy)
+{
+    if (!s) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    const size_t n = (size_t)s->Nx * s->Ny;
+    double *d = nullptr;
+    if (hipMalloc(&d, 3 * n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LB_ENOMEM);
+    }
+    const Params<double> p = make_params<double>(s);
+    hipError_t e = with_type(s, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_moments<T>(bufp<T>(s, state_index(s)), d, d + n, d + 2 * n, s->cs, p, s->stream);
+    });
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && ux) e = hipMemcpyAsync(ux, d + n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && uy)
+        e = hipMemcpyAsync(uy, d + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(dev_status(e));
+    return LB_OK;
+}
+
+int lb_set_probe(lb_sim *s, const double *ax, const double *ay, const double *bx, const double *by)
+{
+    if (!s) return fail(LB_EINVAL);
+    if (!ax && !ay && !bx && !by) {
+        s->probe = false;
+        return LB_OK;
+    }
+    if (!ax || !ay || !bx || !by) return fail(LB_EINVAL);
+    const int Nx = s->Nx, Ny = s->Ny;
+    const size_t n = 2 * (size_t)(Nx + Ny);
+    std::vector<double> h(n);
+    std::memcpy(h.data(), ax, Nx * sizeof(double));
+    std::memcpy(h.data() + Nx, ay, Ny * sizeof(double));
+    std::memcpy(h.data() + Nx + Ny, bx, Nx * sizeof(double));
+    std::memcpy(h.data() + 2 * Nx + Ny, by, Ny * sizeof(double));
+    if (!all_finite(h.data(), n)) return fail(LB_EINVAL);
+    // sum phi.phi = (sum ax^2)(sum ay^2) + (sum bx^2)(sum by^2)
+    double sax = 0, say = 0, sbx = 0, sby = 0;
+    for (int i = 0; i < Nx; ++i) {
+        sax += ax[i] * ax[i];
+        sbx += bx[i] * bx[i];
+    }
+    for (int j = 0; j < Ny; ++j) {
+        say += ay[j] * ay[j];
+        sby += by[j] * by[j];
+    }
+    const double den = sax * say + sbx * sby;
+    if (!(den > 0)) return fail(LB_EINVAL);
+    std::vector<float> h32(h.begin(), h.end());
+    if (!s->d_probe64) {
+        if (hipMalloc(&s->d_probe64, n * sizeof(double)) != hipSuccess ||
+            hipMalloc(&s->d_probe32, n * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LB_ENOMEM);
+        }
+    }
+    if (hipMemcpyAsync(s->d_probe64, h.data(), n * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_probe32, h32.data(), n * sizeof(float), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return fail(LB_EDEVICE);
+    s->probe = true;
+    s->probe_den = den;
+    return LB_OK;
+}
+
+int lb_step(lb_sim *s, int nsteps)
+{
+    if (!s || nsteps < 0) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    for (int i = 0; i < nsteps; ++i) {
+        hipError_t e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return step_once<T>(s, false);
+        });
+        if (e != hipSuccess) return fail(dev_status(e));
+    }
+    return LB_OK;
+}
+
+int lb_reduce(lb_sim *s, double out[5])
+{
+    if (!s || !out) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    hipError_t e = with_type(s, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return reduce_into<T>(s, s->d_out);
+    });
+    double raw[kDiag];
+    if (e == hipSuccess) e = hipMemcpyAsync(raw, s->d_out, sizeof(raw), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(dev_status(e));
+    finish_diag(s, raw, 1.0, out);
+    if (!all_finite(out, kDiag)) return fail(LB_ENAN);
+    return LB_OK;
+}
+
+int lb_run_sampled(lb_sim *s, int nsteps, int every, double *series)
+{
+    if (!s || nsteps < 0 || every < 1 || !series) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    const int nsamp = nsteps / every + 1;
+    double *d_series = nullptr;
+    if (hipMalloc(&d_series, sizeof(double) * kDiag * nsamp) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LB_ENOMEM);
+    }
+    std::vector<int> fused(nsamp, 0);
+    hipError_t e = hipSuccess;
+    for (int t = 0; t <= nsteps && e == hipSuccess; ++t) {
+        const bool sample = (t % every) == 0;
+        const int idx = t / every;
+        if (t == nsteps) {
+            if (sample)
+                e = with_type(s, [&](auto *tag) {
+                    using T = std::remove_pointer_t<decltype(tag)>;
+                    return reduce_into<T>(s, d_series + kDiag * idx);
+                });
+            break;
+        }
+        e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return step_once<T>(s, sample);
+        });
+        if (e == hipSuccess && sample) {
+            e = launch_diag_finalize(s->d_partial, diag_blocks_fused(s), d_series + kDiag * idx, s->stream);
+            fused[idx] = 1;
+        }
+    }
+    std::vector<double> raw((size_t)kDiag * nsamp);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(raw.data(), d_series, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d_series);
+    if (e != hipSuccess) return fail(dev_status(e));
+    // fused CS sums are in lattice velocity units (u / c_l); FD and the
+    // stand-alone reduction use physical velocities
+    for (int i = 0; i < nsamp; ++i)
+        finish_diag(s, raw.data() + kDiag * i, (fused[i] && s->cs) ? s->mi.cl : 1.0, series + kDiag * i);
+    if (!all_finite(series, (size_t)kDiag * nsamp)) return fail(LB_ENAN);
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// lb_aux.hip -- set-up and read-out kernels of the lattice Boltzmann library:
+// equilibrium initialisation, canonical state transfer, moments and the
+// stand-alone FP64 diagnostics.  All arithmetic here is FP64 whatever the
+// storage precision; none of these kernels is on the time-step path.
+//
+// Collision-streaming storage holds post-collision values at their source
+// node, so the canonical (pre-collision) value f_k(x) is read from x - e_k
+// ("pull") and written to x - e_k ("push").  Finite-difference storage holds
+// f_k(x) at x.
+#include "lb_diag.h"
+#include "lb_internal.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr int kAuxThreads = 256;
+constexpr int kReduceMaxBlocks = 1024;
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Shifted order-N equilibrium g_eq_k = f_eq_k - w_k rho0 =
+// w_k [drho + rho sum_{1 <= n+m <= N} He_n(xi_i) He_m(xi_j) ax^n ay^m / (n! m!)],
+// with ax, ay the velocity in units of c_s (Section 1).
+__device__ double feq_shifted(const Params<double> &p, int k, double drho, double rho, double ax, double ay)
+{
+    double px[kMaxN + 1], py[kMaxN + 1];
+    px[0] = py[0] = 1.0;
+    for (int n = 1; n <= p.N; ++n) {
+        px[n] = px[n - 1] * ax;
+        py[n] = py[n - 1] * ay;
+    }
+    const int i = p.ki[k], j = p.kj[k];
+    double s = 0.0;
+    for (int n = 0; n <= p.N; ++n)
+        for (int m = 0; n + m <= p.N; ++m)
+            if (n + m > 0) s += (p.hc[i][n] * px[n]) * (p.hc[j][m] * py[m]);
+    return p.w[k] * (drho + rho * s);
+}
+
+// Storage address of the value of population k that the canonical state
+// holds at node (x, y).
+__device__ __forceinline__ long long store_index(const Params<double> &p, bool cs, int k, int x, int y)
+{
+    int xs = x, ys = y;
+    if (cs) {
+        const int ex = p.ki[k] - 1, ey = p.kj[k] - 1;
+        xs = x - ex;
+        ys = wrapi(y - ey, p.Ny);
+        if (!p.fixed_x) xs = wrapi(xs, p.Nx);  // with fixed ends xs = -1 / Nx is a ghost column
+    }
+    return (long long)k * p.plane + (long long)ys * p.pitch + p.xoff + xs;
+}
+
+template <typename T>
+__device__ __forceinline__ double ldd(const T *ptr) { return (double)ld(ptr); }
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void init_kernel(T *dst, const double *rho, const double *ux,
+                                                           const double *uy, bool cs, const Params<double> p)
+{
+    const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
+    if (n >= (long long)p.Nx * p.Ny) return;
+    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    const double r = rho[n];
+    const double ax = ux[n] / p.cs, ay = uy[n] / p.cs;
+    for (int k = 0; k < p.K; ++k) store_from(dst + store_index(p, cs, k, x, y), feq_shifted(p, k, r - p.rho0, r, ax, ay));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void fill_ghosts_kernel(T *buf, const Params<double> p)
+{
+    const int n = blockIdx.x * kAuxThreads + threadIdx.x;
+    if (n >= p.K * p.Ny) return;
+    const int k = n / p.Ny, y = n % p.Ny;
+    T *row = buf + (long long)k * p.plane + (long long)y * p.pitch;
+    store_from(row, p.ghost_l[k]);
+    store_from(row + p.xoff + p.Nx, p.ghost_r[k]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void get_state_kernel(const T *src, double *f, bool cs,
+                                                                const Params<double> p)
+{
+    const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
+    const long long nodes = (long long)p.Nx * p.Ny;
+    if (n >= nodes) return;
+    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    for (int k = 0; k < p.K; ++k) f[k * nodes + n] = ldd(src + store_index(p, cs, k, x, y)) + p.w[k] * p.rho0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void set_state_kernel(T *dst, const double *f, bool cs,
+                                                                const Params<double> p)
+{
+    const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
+    const long long nodes = (long long)p.Nx * p.Ny;
+    if (n >= nodes) return;
+    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    for (int k = 0; k < p.K; ++k) store_from(dst + store_index(p, cs, k, x, y), f[k * nodes + n] - p.w[k] * p.rho0);
+}
+
+// moments of node n: drho = sum g_k, j = sum g_k v_k (sum w_k v_k = 0)
+template <typename T>
+__device__ __forceinline__ void node_moments(const T *src, bool cs, const Params<double> &p, int x, int y,
+                                             double &drho, double &jx, double &jy)
+{
+    drho = jx = jy = 0.0;
+    for (int k = 0; k < p.K; ++k) {
+        const double g = ldd(src + store_index(p, cs, k, x, y));
+        drho += g;
+        jx += g * p.vx[k];
+        jy += g * p.vy[k];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void moments_kernel(const T *src, double *rho, double *ux, double *uy,
+                                                              bool cs, const Params<double> p)
+{
+    const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
+    if (n >= (long long)p.Nx * p.Ny) return;
+    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    double drho, jx, jy;
+    node_moments(src, cs, p, x, y, drho, jx, jy);
+    const double r = p.rho0 + drho;
+    if (rho) rho[n] = r;
+    if (ux) ux[n] = jx / r;
+    if (uy) uy[n] = jy / r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void reduce_kernel(const T *src, bool cs, const Params<double> p,
+                                                             const DiagArgs<double> d)
+{
+    const long long nodes = (long long)p.Nx * p.Ny;
+    DiagAcc acc;
+    for (long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x; n < nodes;
+         n += (long long)gridDim.x * kAuxThreads) {
+        const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+        double drho, jx, jy;
+        node_moments(src, cs, p, x, y, drho, jx, jy);
+        const double r = p.rho0 + drho, ux = jx / r, uy = jy / r;
+        acc.v[0] += drho;
+        acc.v[1] += jx;
+        acc.v[2] += jy;
+        acc.v[3] += 0.5 * r * (ux * ux + uy * uy);
+        if (d.ax) acc.v[4] += ux * (d.ax[x] * d.ay[y]) + uy * (d.bx[x] * d.by[y]);
+    }
+    block_diag_store(acc, d.partial, blockIdx.x);
+}
+
+// One block: thread t sums partials t, t + 256, ... in order, then a fixed
+// pairwise tree over the 256 thread sums.
+__global__ __launch_bounds__(kAuxThreads) void diag_finalize_kernel(const double *partial, int nblocks, double *out)
+{
+    __shared__ double s[kDiag][kAuxThreads];
+    const int t = threadIdx.x;
+    double a[kDiag] = {0, 0, 0, 0, 0};
+    for (int b = t; b < nblocks; b += kAuxThreads)
+        for (int i = 0; i < kDiag; ++i) a[i] += partial[(long long)b * kDiag + i];
+    for (int i = 0; i < kDiag; ++i) s[i][t] = a[i];
+    __syncthreads();
+    for (int h = kAuxThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int i = 0; i < kDiag; ++i) s[i][t] += s[i][t + h];
+        __syncthreads();
+    }
+    if (t < kDiag) out[t] = s[t][0];
+}
+
+unsigned grid_for(long long n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
+
+}  // namespace
+
+int reduce_diag_blocks(int Nx, int Ny)
+{
+    long long b = ((long long)Nx * Ny + kAuxThreads - 1) / kAuxThreads;
+    return (int)(b < kReduceMaxBlocks ? b : kReduceMaxBlocks);
+}
+
+template <typename T>
+hipError_t launch_init(T *dst, const double *rho, const double *ux, const double *uy, bool cs,
+                       const Params<double> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_kernel<T>, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s, dst, rho,
+                       ux, uy, cs, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_ghosts(T *buf, const Params<double> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(grid_for((long long)p.K * p.Ny)), dim3(kAuxThreads), 0, s, buf,
+                       p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_get_state(const T *src, double *f, bool cs, const Params<double> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(get_state_kernel<T>, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s, src, f,
+                       cs, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_set_state(T *dst, const double *f, bool cs, const Params<double> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_state_kernel<T>, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s, dst, f,
+                       cs, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_moments(const T *src, double *rho, double *ux, double *uy, bool cs, const Params<double> &p,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(moments_kernel<T>, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s, src,
+                       rho, ux, uy, cs, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reduce(const T *src, bool cs, const Params<double> &p, const DiagArgs<double> &diag,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel<T>, dim3(reduce_diag_blocks(p.Nx, p.Ny)), dim3(kAuxThreads), 0, s, src, cs, p,
+                       diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_finalize(const double *partial, int nblocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(diag_finalize_kernel, dim3(1), dim3(kAuxThreads), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
+#define LB_AUX_INSTANTIATE(T)                                                                                     \
+    template hipError_t launch_init<T>(T *, const double *, const double *, const double *, bool,                 \
+                                       const Params<double> &, hipStream_t);                                      \
+    template hipError_t launch_fill_ghosts<T>(T *, const Params<double> &, hipStream_t);                          \
+    template hipError_t launch_get_state<T>(const T *, double *, bool, const Params<double> &, hipStream_t);      \
+    template hipError_t launch_set_state<T>(T *, const double *, bool, const Params<double> &, hipStream_t);      \
+    template hipError_t launch_moments<T>(const T *, double *, double *, double *, bool, const Params<double> &,  \
+                                          hipStream_t);                                                           \
+    template hipError_t launch_reduce<T>(const T *, bool, const Params<double> &, const DiagArgs<double> &,       \
+                                         hipStream_t);
+
+LB_AUX_INSTANTIATE(float)
+LB_AUX_INSTANTIATE(__half)
+LB_AUX_INSTANTIATE(double)
+
+}  // namespace lbm

@@ -1,0 +1,99 @@
+// lb_internal.h -- types shared by the host runtime and the HIP kernels of
+// the lattice Boltzmann library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lb.h"
+
+namespace lbm {
+
+constexpr int kMaxQ = 6;          // largest per-axis Gauss-Hermite order
+constexpr int kMaxK = kMaxQ * kMaxQ;
+constexpr int kMaxN = kMaxQ - 1;  // largest equilibrium order
+constexpr int kDiag = 5;          // sum drho, sum jx, sum jy, sum rho|u|^2/2, sum u.phi
+
+// Per-simulation constants, passed to every kernel by value (kernel
+// arguments live in the constant cache; every index into these arrays is
+// wave-uniform).  CT is the arithmetic type (float or double).
+template <typename CT>
+struct Params {
+    int Nx, Ny;
+    int pitch;        // elements between rows of one population plane
+    int xoff;         // column of node x = 0 inside a row (1 with ghost columns)
+    long long plane;  // elements between population planes
+    int K, Q, N;
+    int fixed_x;      // fixed-value x ends
+    CT rho0;          // shift: stored g_k = f_k - w_k rho0
+    CT cs;            // sound speed
+    CT omega;         // CS: dt / tau
+    CT dt, inv_ds, inv_tau, eps;  // FD
+    CT w[kMaxK];
+    CT vx[kMaxK], vy[kMaxK];      // physical velocities
+    int ki[kMaxK], kj[kMaxK];     // per-axis root index of population k
+    CT ghost_l[kMaxK], ghost_r[kMaxK];  // stored end equilibria: w_k (rho_end - rho0)
+    CT hc[kMaxQ][kMaxN + 1];      // He_n(xi_i) / n!, xi_i = root i in units of c_s
+};
+
+// Fused or stand-alone diagnostics: per-block FP64 partial sums.
+template <typename CT>
+struct DiagArgs {
+    double *partial;              // [blocks][kDiag]
+    const CT *ax, *ay, *bx, *by;  // separable probe, NULL when unset
+};
+
+// Storage conversions: the state is stored as float, half or double; the
+// arithmetic type is float for the first two and double for the last.
+__device__ __forceinline__ void store_from(float *p, float v) { *p = v; }
+__device__ __forceinline__ void store_from(__half *p, float v) { *p = __float2half_rn(v); }
+__device__ __forceinline__ void store_from(double *p, double v) { *p = v; }
+__device__ __forceinline__ void store_from(float *p, double v) { *p = (float)v; }
+__device__ __forceinline__ void store_from(__half *p, double v) { *p = __builtin_bit_cast(__half, (_Float16)v); }
+
+template <typename T> struct Arith { using type = float; };
+template <> struct Arith<double> { using type = double; };
+
+template <typename T>
+__device__ __forceinline__ typename Arith<T>::type ld(const T *p);
+template <> __device__ __forceinline__ float ld<float>(const float *p) { return *p; }
+template <> __device__ __forceinline__ float ld<__half>(const __half *p) { return __half2float(*p); }
+template <> __device__ __forceinline__ double ld<double>(const double *p) { return *p; }
+
+// Hot-path launchers (lb_cs.hip, lb_fd.hip).  `diag` non-NULL fuses the
+// diagnostics of the step's input state.
+template <typename T>
+hipError_t launch_cs_step(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
+                          const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s);
+template <typename T>
+hipError_t launch_fd_stage(const T *src, const T *gn, T *out, int stage, const Params<typename Arith<T>::type> &p,
+                           const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s);
+int cs_diag_blocks(int Nx, int Ny);
+int fd_diag_blocks(int Nx, int Ny);
+
+// Auxiliary launchers (lb_aux.hip), all in FP64 arithmetic.  `cs` selects
+// the pull / push mapping of the collision-streaming storage.
+template <typename T>
+hipError_t launch_init(T *dst, const double *rho, const double *ux, const double *uy, bool cs,
+                       const Params<double> &p, hipStream_t s);
+template <typename T>
+hipError_t launch_get_state(const T *src, double *f, bool cs, const Params<double> &p, hipStream_t s);
+template <typename T>
+hipError_t launch_set_state(T *dst, const double *f, bool cs, const Params<double> &p, hipStream_t s);
+template <typename T>
+hipError_t launch_moments(const T *src, double *rho, double *ux, double *uy, bool cs, const Params<double> &p,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_reduce(const T *src, bool cs, const Params<double> &p, const DiagArgs<double> &diag,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_fill_ghosts(T *buf, const Params<double> &p, hipStream_t s);
+int reduce_diag_blocks(int Nx, int Ny);
+
+// Deterministic sum of nblocks partials into out[kDiag] (device memory).
+hipError_t launch_diag_finalize(const double *partial, int nblocks, double *out, hipStream_t s);
+
+}  // namespace lbm

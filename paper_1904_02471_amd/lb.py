@@ -1,0 +1,255 @@
+"""ctypes binding of liblbm.so, with the names of the C ABI in include/lb.h.
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Importing this module loads liblbm.so and fails loudly when it is
+missing; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LB_CS_D2Q9, LB_FD_D2Q9, LB_FD_D2Q16, LB_FD_D2Q25, LB_FD_D2Q36 = 0, 1, 2, 3, 4
+LB_FP32, LB_FP16_SHIFTED, LB_FP64 = 0, 1 << 8, 2 << 8
+LB_OK, LB_EINVAL, LB_ECFL, LB_ESTIFF, LB_ENOMEM, LB_EDEVICE, LB_ENAN, LB_EBUSY, LB_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_FD_D2Q36: 6}
+
+# every symbol include/lb.h declares (checked by the CPU test-suite)
+EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
+           "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_run_sampled",
+           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_stream", "lb_synchronize", "lb_device_bytes"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblbm.so is not built (%s); run paper_1904_02471_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "lb_create": (_vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_int]),
+        "lb_destroy": (None, [_vp]),
+        "lb_last_error": (ctypes.c_int, []),
+        "lb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "lb_model_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp]),
+        "lb_set_bc_x": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+        "lb_set_weno_eps": (ctypes.c_int, [_vp, ctypes.c_double]),
+        "lb_init": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+        "lb_step": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+        "lb_set_probe": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+        "lb_reduce": (ctypes.c_int, [_vp, _dp]),
+        "lb_run_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
+        "lb_get_state": (ctypes.c_int, [_vp, _dp]),
+        "lb_set_state": (ctypes.c_int, [_vp, _dp]),
+        "lb_steps_done": (ctypes.c_longlong, [_vp]),
+        "lb_set_stream": (ctypes.c_int, [_vp, _vp]),
+        "lb_synchronize": (ctypes.c_int, [_vp]),
+        "lb_device_bytes": (ctypes.c_size_t, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _f64(a, shape):
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape), dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != LB_OK:
+        raise LBError(rc, what)
+    return rc
+
+
+def strerror(code):
+    return _lib.lb_strerror(int(code)).decode()
+
+
+def lb_last_error():
+    return _lib.lb_last_error()
+
+
+def lb_model_info(model, ds=1.0, dt=1.0):
+    """(vx, vy, w, cs) of a model."""
+    vx, vy, w, cs = np.zeros(64), np.zeros(64), np.zeros(64), np.zeros(1)
+    K = _lib.lb_model_info(int(model), float(ds), float(dt), _ptr(vx), _ptr(vy), _ptr(w), _ptr(cs))
+    if K < 0:
+        raise LBError(K, "lb_model_info")
+    return vx[:K].copy(), vy[:K].copy(), w[:K].copy(), float(cs[0])
+
+
+class Sim:
+    """Handle of one simulation: the lb_* calls taking an lb_sim* are its
+    methods (same names without the prefix) and the module-level lb_*
+    functions below."""
+
+    def __init__(self, model, Nx, Ny, tau, dt, ds, N=2, precision=LB_FP32):
+        self.model, self.Nx, self.Ny, self.N = int(model), int(Nx), int(Ny), int(N)
+        self.tau, self.dt, self.ds, self.precision = float(tau), float(dt), float(ds), int(precision)
+        h = _lib.lb_create(self.model | self.precision, self.Nx, self.Ny, self.tau, self.dt, self.ds, self.N)
+        if not h:
+            raise LBError(_lib.lb_last_error(), "lb_create")
+        self._h = h
+        q = Q_OF_MODEL[self.model]
+        self.K = q * q
+        self.vx, self.vy, self.w, self.cs = lb_model_info(self.model, ds, dt)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _lib.lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_bc_x(self, rho_left, rho_right):
+        _check(_lib.lb_set_bc_x(self._h, float(rho_left), float(rho_right)), "lb_set_bc_x")
+
+    def set_weno_eps(self, eps):
+        _check(_lib.lb_set_weno_eps(self._h, float(eps)), "lb_set_weno_eps")
+
+    def init(self, rho, ux, uy):
+        shp = (self.Ny, self.Nx)
+        r, x, y = _f64(rho, shp), _f64(ux, shp), _f64(uy, shp)
+        _check(_lib.lb_init(self._h, _ptr(r), _ptr(x), _ptr(y)), "lb_init")
+
+    def step(self, n=1):
+        _check(_lib.lb_step(self._h, int(n)), "lb_step")
+
+    def moments(self):
+        shp = (self.Ny, self.Nx)
+        r, x, y = np.empty(shp), np.empty(shp), np.empty(shp)
+        _check(_lib.lb_moments(self._h, _ptr(r), _ptr(x), _ptr(y)), "lb_moments")
+        return r, x, y
+
+    def set_probe(self, ax=None, ay=None, bx=None, by=None):
+        if ax is None:
+            _check(_lib.lb_set_probe(self._h, None, None, None, None), "lb_set_probe")
+            return
+        a = [_f64(v, (n,)) for v, n in ((ax, self.Nx), (ay, self.Ny), (bx, self.Nx), (by, self.Ny))]
+        _check(_lib.lb_set_probe(self._h, *[_ptr(v) for v in a]), "lb_set_probe")
+
+    def reduce(self):
+        out = np.empty(5)
+        _check(_lib.lb_reduce(self._h, _ptr(out)), "lb_reduce")
+        return out
+
+    def run_sampled(self, nsteps, every):
+        out = np.empty((int(nsteps) // int(every) + 1, 5))
+        _check(_lib.lb_run_sampled(self._h, int(nsteps), int(every), _ptr(out)), "lb_run_sampled")
+        return out
+
+    def get_state(self):
+        f = np.empty((self.K, self.Ny, self.Nx))
+        _check(_lib.lb_get_state(self._h, _ptr(f)), "lb_get_state")
+        return f
+
+    def set_state(self, f):
+        f = _f64(f, (self.K, self.Ny, self.Nx))
+        _check(_lib.lb_set_state(self._h, _ptr(f)), "lb_set_state")
+
+    def steps_done(self):
+        return _lib.lb_steps_done(self._h)
+
+    def set_stream(self, stream_handle):
+        """stream_handle: an integer hipStream_t (e.g. torch.cuda.Stream().cuda_stream) or 0/None."""
+        _check(_lib.lb_set_stream(self._h, ctypes.c_void_p(int(stream_handle or 0))), "lb_set_stream")
+
+    def synchronize(self):
+        _check(_lib.lb_synchronize(self._h), "lb_synchronize")
+
+    def device_bytes(self):
+        return _lib.lb_device_bytes(self._h)
+
+
+# module-level functions with the C names
+def lb_create(model_flags, Nx, Ny, tau, dt, ds, N):
+    return Sim(model_flags & 0xFF, Nx, Ny, tau, dt, ds, N, precision=model_flags & (3 << 8))
+
+
+def lb_destroy(sim):
+    sim.destroy()
+
+
+def lb_set_bc_x(sim, rho_left, rho_right):
+    sim.set_bc_x(rho_left, rho_right)
+
+
+def lb_set_weno_eps(sim, eps):
+    sim.set_weno_eps(eps)
+
+
+def lb_init(sim, rho, ux, uy):
+    sim.init(rho, ux, uy)
+
+
+def lb_step(sim, nsteps=1):
+    sim.step(nsteps)
+
+
+def lb_moments(sim):
+    return sim.moments()
+
+
+def lb_set_probe(sim, ax=None, ay=None, bx=None, by=None):
+    sim.set_probe(ax, ay, bx, by)
+
+
+def lb_reduce(sim):
+    return sim.reduce()
+
+
+def lb_run_sampled(sim, nsteps, every):
+    return sim.run_sampled(nsteps, every)
+
+
+def lb_get_state(sim):
+    return sim.get_state()
+
+
+def lb_set_state(sim, f):
+    sim.set_state(f)
+
+
+def lb_steps_done(sim):
+    return sim.steps_done()
+
+
+def lb_set_stream(sim, stream_handle):
+    sim.set_stream(stream_handle)
+
+
+def lb_synchronize(sim):
+    sim.synchronize()
+
+
+def lb_device_bytes(sim):
+    return sim.device_bytes()

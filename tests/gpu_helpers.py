@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU parity tests: paired GPU / oracle simulations
+and the tolerances derived from the arithmetic.
+
+Tolerances (per element of the canonical state f, absolute):
+  FP64 storage: both sides compute in double; they differ by summation order
+      and fused multiply-adds only: 1e-13 * (n + 1) * max|f|.
+  FP32 storage: the stored shifted value g = f - w rho0 carries a relative
+      rounding of u32 = 2^-24 per step, and the O(1) sums (rho = rho0 + drho)
+      an absolute rounding of u32; each step adds at most ~C u32 max|f| with
+      C = 32 (about 30 rounded operations feed one output), so
+      tol = 32 u32 (n + 1) max|f|.
+  FP16 storage: the stored g carries a relative rounding of u16 = 2^-11 per
+      step: tol = 2 u16 (n + 1) max|g| + the FP32 bound.
+"""
+import numpy as np
+
+import oracle
+from paper_1904_02471_amd import lb
+
+U32 = 2.0 ** -24
+U16 = 2.0 ** -11
+
+ORACLE_MODEL = {lb.LB_CS_D2Q9: oracle.CS_D2Q9, lb.LB_FD_D2Q9: oracle.FD_D2Q9, lb.LB_FD_D2Q16: oracle.FD_D2Q16,
+                lb.LB_FD_D2Q25: oracle.FD_D2Q25, lb.LB_FD_D2Q36: oracle.FD_D2Q36}
+PREC_NAME = {lb.LB_FP32: "fp32", lb.LB_FP16_SHIFTED: "fp16", lb.LB_FP64: "fp64"}
+
+
+def pair(model, Nx, Ny, tau, dt, ds, N, prec, bc=None, eps=None):
+    g = lb.Sim(model, Nx, Ny, tau, dt, ds, N, precision=prec)
+    o = oracle.OracleSim(ORACLE_MODEL[model], Nx, Ny, tau, dt, ds, N)
+    if bc is not None:
+        g.set_bc_x(*bc)
+        o.set_bc_x(*bc)
+    if eps is not None:
+        g.set_weno_eps(eps)
+        o.set_weno_eps(eps)
+    return g, o
+
+
+def tolerance(prec, nsteps, f_ref, w, rho0):
+    fmax = float(np.max(np.abs(f_ref)))
+    gmax = float(np.max(np.abs(f_ref - w[:, None, None] * rho0)))
+    if prec == lb.LB_FP64:
+        return 1e-13 * (nsteps + 1) * fmax
+    tol = 32 * U32 * (nsteps + 1) * fmax
+    if prec == lb.LB_FP16_SHIFTED:
+        tol += 2 * U16 * (nsteps + 1) * gmax
+    return tol
+
+
+def assert_state_close(gpu_f, orc_f, tol, what):
+    err = np.abs(gpu_f - orc_f)
+    i = np.unravel_index(np.argmax(err), err.shape)
+    print("%s: max|df| = %.3e at %s (tol %.3e)" % (what, err[i], i, tol), flush=True)
+    assert err[i] <= tol, "%s: max|df| %.3e at %s > tol %.3e" % (what, err[i], i, tol)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))

@@ -1,0 +1,103 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the
+header declares, and its host-side logic (velocity tables, parameter
+validation, unit relations) is right.  No compute call needs a GPU here."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tests.conftest import ROOT
+
+from paper_1904_02471_amd import lb, units
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lb._lib, n), n
+    assert sorted(lb.EXPORTS) == names
+
+
+def test_library_is_built_for_gfx950():
+    data = open(lb.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+@pytest.mark.parametrize("model,Q", [(lb.LB_FD_D2Q9, 3), (lb.LB_FD_D2Q16, 4), (lb.LB_FD_D2Q25, 5), (lb.LB_FD_D2Q36, 6)])
+def test_model_tables_match_library_rule(model, Q):
+    xr, wr = np.polynomial.hermite_e.hermegauss(Q)
+    wr = wr / wr.sum()
+    vx, vy, w, cs = lb.lb_model_info(model)
+    assert cs == 1.0
+    for j in range(Q):
+        for i in range(Q):
+            k = j * Q + i
+            assert vx[k] == pytest.approx(xr[i], abs=1e-14)
+            assert vy[k] == pytest.approx(xr[j], abs=1e-14)
+            assert w[k] == pytest.approx(wr[i] * wr[j], rel=1e-13)
+    # odd rules keep an exact zero velocity
+    if Q % 2:
+        assert vx[Q // 2] == 0.0
+
+
+def test_d2q9_tables():
+    vx, vy, w, cs = lb.lb_model_info(lb.LB_CS_D2Q9, 1.0, 1.0 / math.sqrt(3))
+    e = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]])
+    np.testing.assert_allclose(vx, e[:, 0] * math.sqrt(3), atol=1e-15)
+    np.testing.assert_allclose(vy, e[:, 1] * math.sqrt(3), atol=1e-15)
+    np.testing.assert_allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, atol=1e-15)
+    assert cs == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((lb.LB_CS_D2Q9, 8, 8, 0.4, 1.0, 1.0, 2), lb.LB_EINVAL),    # tau <= dt/2: negative viscosity
+    ((lb.LB_CS_D2Q9, 8, 8, 0.8, 1.0, 1.0, 3), lb.LB_EINVAL),    # CS needs N = 2
+    ((lb.LB_CS_D2Q9, 0, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),    # empty grid
+    ((lb.LB_FD_D2Q16, 8, 8, 1e-3, 1e-3, 0.1, 4), lb.LB_EINVAL),  # N > Q - 1
+    ((lb.LB_FD_D2Q16, 8, 8, 1e-3, 1e-3, 0.1, 0), lb.LB_EINVAL),
+    ((lb.LB_FD_D2Q16, 8, 8, 1.0, 0.05, 0.1, 3), lb.LB_ECFL),    # 2.334 * 0.05 / 0.1 > 1
+    ((lb.LB_FD_D2Q16, 8, 8, 1e-3, 2e-3, 0.1, 3), lb.LB_ESTIFF),  # dt > tau
+    ((7, 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),                # unknown model
+    ((lb.LB_CS_D2Q9 | (3 << 8), 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),
+    ((lb.LB_CS_D2Q9, 8, 8, float("nan"), 1.0, 1.0, 2), lb.LB_EINVAL),
+])
+def test_create_validation(args, code):
+    h = lb._lib.lb_create(*args)
+    assert not h
+    assert lb.lb_last_error() == code
+    assert lb.strerror(code) not in ("", "unknown status")
+
+
+def test_null_handles_are_rejected():
+    assert lb._lib.lb_step(None, 1) == lb.LB_EINVAL
+    assert lb._lib.lb_reduce(None, None) == lb.LB_EINVAL
+    assert lb._lib.lb_steps_done(None) == -1
+    lb._lib.lb_destroy(None)
+
+
+def test_units_match_printed_values(golden):
+    g = golden("tau_conversion.txt")
+    for key in ("a", "b"):
+        got = units.tau_lu_from_fd(float(g["shock_tau_fd_" + key]), int(g["shock_n"]))
+        printed = g["shock_tau_lu_" + key]
+        d = len(printed.split(".")[1])
+        assert math.floor(got * 10 ** d + 1e-9) / 10 ** d == pytest.approx(float(printed), abs=1e-12)
+    for n, printed in zip(g["table_n"].split(), g["table_tau_lu"].split()):
+        got = units.tau_lu_from_fd(float(g["table_tau_fd"]), int(n))
+        assert math.floor(got * 1e4 + 1e-9) / 1e4 == pytest.approx(float(printed), abs=1e-12)
+        assert units.nu_cs(got, 1 / math.sqrt(3), 1.0) == pytest.approx(int(n) * float(g["table_tau_fd"]), rel=1e-12)
+    t = golden("time_steps.txt")
+    assert abs(units.cs_step_in_fd_time(int(t["n"])) - float(t["dt_cs_fd"])) < 5e-7
+    # standard lattice units bridge
+    assert units.tau_fd_from_std(0.6, 512) == pytest.approx(1.12764e-4, rel=1e-5)
+    assert units.tau_std_from_lu(units.tau_lu_from_fd(units.tau_fd_from_std(0.8, 64), 64)) == pytest.approx(0.8)
+    assert units.fd_time_step(5e-4, 1 / 2048, 3.324257, 0.5) == pytest.approx(7.3442e-5, rel=1e-4)
