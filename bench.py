@@ -1,0 +1,213 @@
+"""Benchmark of the lattice Boltzmann hot path on one MI355X.
+
+One step = one collision-streaming D2Q9 step and one finite-difference
+D2Q16 step (three Runge-Kutta stage launches) on a Taylor-Green vortex,
+each with the FP64 diagnostics fused into the step kernels every 10th step.
+Default workload: 2048 x 2048 periodic, rho0 = 1, u0 = 0.01 (standard
+lattice units), CS tau = 0.6, FD D2Q16 with N = 3 at the same viscosity
+(tau_FD = (tau - 1/2) / (sqrt(3) N)), dt_FD = min(CFL 0.5, tau_FD), FP32
+storage.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS of the whole step (node updates per second:
+one update advances a node by one CS step and one FD step), per-model MLUPS
+and HBM fractions, the roofline of the dominant kernel (the FD stage) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--sample-every", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["cs", "fd"], default=None,
+                    help="time one model alone (profiling runs); the JSON line is then per model")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a plain device copy of the CS state size (counter calibration)")
+    return ap.parse_args()
+
+
+def make_sims(lb, workloads, units, n, stream):
+    u0 = 0.01
+    cs = lb.Sim(lb.LB_CS_D2Q9, n, n, 0.6, 1.0, 1.0, 2, precision=lb.LB_FP32)
+    r, ux, uy, _ = workloads.taylor_green(n, n, u0, 1.0 / 3.0)
+    cs.set_stream(stream)
+    cs.init(r, ux, uy)
+    ax, ay, bx, by = workloads.separable_pattern("tgv", n, n)
+    cs.set_probe(ax, ay, bx, by)
+
+    ds = 1.0 / n
+    tau_fd = units.tau_fd_from_std(0.6, n)
+    vmax = lb.lb_model_info(lb.LB_FD_D2Q16)[0].max()
+    dt_fd = units.fd_time_step(tau_fd, ds, vmax, 0.5)
+    fd = lb.Sim(lb.LB_FD_D2Q16, n, n, tau_fd, dt_fd, ds, 3, precision=lb.LB_FP32)
+    r, ux, uy, _ = workloads.taylor_green(n, n, units.velocity_fd_from_std(u0), 1.0)
+    fd.set_stream(stream)
+    fd.init(r, ux, uy)
+    fd.set_probe(ax, ay, bx, by)
+    return cs, fd, {"tau_fd": tau_fd, "dt_fd": dt_fd}
+
+
+def cpu_baseline(every):
+    """FP64 oracle on a bounded sample of the same workload: CS D2Q9 512^2 x 16
+    steps and FD D2Q16 256^2 x 4 steps, diagnostics every `every` steps."""
+    import oracle
+    from paper_1904_02471_amd import units, workloads
+
+    def run(model, n, steps):
+        if model == oracle.CS_D2Q9:
+            s = oracle.OracleSim(model, n, n, 0.6, 1.0, 1.0, 2)
+            r, ux, uy, (px, py) = workloads.taylor_green(n, n, 0.01, 1.0 / 3.0)
+        else:
+            ds = 1.0 / n
+            tau = units.tau_fd_from_std(0.6, n)
+            s = oracle.OracleSim(model, n, n, tau, units.fd_time_step(tau, ds, 2.3344142183389773, 0.5), ds, 3)
+            r, ux, uy, (px, py) = workloads.taylor_green(n, n, units.velocity_fd_from_std(0.01), 1.0)
+        s.init(r, ux, uy)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            if i % every == 0:
+                s.reduce(px, py)
+            s.step(1)
+        return (time.perf_counter() - t0) / (n * n * steps)
+
+    t_cs = run(oracle.CS_D2Q9, 512, 16)
+    t_fd = run(oracle.FD_D2Q16, 256, 4)
+    return {"value": 1e-6 / (t_cs + t_fd), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "FP64 C oracle, single thread: CS D2Q9 TGV 512x512 x 16 steps (%.3f MLUPS) + "
+                      "FD D2Q16 TGV 256x256 x 4 steps (%.4f MLUPS), diagnostics every %d steps; value = "
+                      "1 / (t_cs + t_fd) per node" % (1e-6 / t_cs, 1e-6 / t_fd, every)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the hot path here is one simulation per GPU; "
+              "see the sharding notes in DESIGN.md. Requested --gpus %d." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1904_02471_amd import lb, units, workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream(device=0)
+    n, K, W, every = args.size, args.steps, args.warmup, args.sample_every
+    cs, fd, prm = make_sims(lb, workloads, units, n, stream.cuda_stream)
+    cap = (K + W) // every + 2
+    cs.series_reserve(cap)
+    fd.series_reserve(cap)
+    run_cs = args.only in (None, "cs")
+    run_fd = args.only in (None, "fd")
+
+    def step():
+        if run_cs:
+            cs.step_sampled(1, every)
+        if run_fd:
+            fd.step_sampled(1, every)
+
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    cs.series_read()
+    fd.series_read()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i in range(K):
+            ev[i][0].record(stream)
+            if run_cs:
+                cs.step_sampled(1, every)
+            ev[i][1].record(stream)
+            if run_fd:
+                fd.step_sampled(1, every)
+            ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cs_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    fd_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    ser_cs = cs.series_read()
+    ser_fd = fd.series_read()
+    assert np.all(np.isfinite(ser_cs)) and np.all(np.isfinite(ser_fd))
+
+    nodes = n * n
+    ms_per_step = wall * 1e3 / K
+    bytes_cs = 2 * 9 * 4 * nodes                 # read + write 9 FP32 values per node
+    bytes_fd_stage = (8 * 16 * 4 * nodes) / 3.0  # 8 K s per step over 3 stage launches
+    cs_gbs = bytes_cs / (cs_ms * 1e-3) / 1e9 if run_cs else 0.0
+    fd_stage_ms = fd_ms / 3.0
+    fd_gbs = bytes_fd_stage / (fd_stage_ms * 1e-3) / 1e9 if run_fd else 0.0
+    value = nodes / (ms_per_step * 1e-3) / 1e6
+
+    line = {
+        "metric": "MLUPS & % HBM peak (CS D2Q9, FD D2Q16); batched sims/s + p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (closed-form Taylor-Green initial state; the paper uses no dataset)",
+        "config": {
+            "workload": "Taylor-Green vortex %dx%d periodic, u0=0.01, rho0=1: CS D2Q9 tau=0.6 (ds=dt=1) + "
+                        "FD D2Q16 N=3 WENO-5/RK-3 at matched viscosity (tau_FD=%.5e, dt_FD=%.5e), FP32 storage "
+                        "(shifted), FP64 diagnostics fused every %d steps; one update = one node advanced by "
+                        "one CS step and one FD step" % (n, n, prm["tau_fd"], prm["dt_fd"], every),
+            "grid": [n, n],
+            "models": ["cs_d2q9" if run_cs else None, "fd_d2q16" if run_fd else None],
+        },
+        "cs_d2q9": {"ms_per_step": round(cs_ms, 5),
+                    "mlups": round(nodes / (cs_ms * 1e-3) / 1e6, 1) if run_cs else None,
+                    "achieved_gbs": round(cs_gbs, 1), "hbm_frac": round(cs_gbs / HBM_PEAK_GBS, 4),
+                    "bytes_per_node_step": 72},
+        "fd_d2q16": {"ms_per_step": round(fd_ms, 5),
+                     "mlups": round(nodes / (fd_ms * 1e-3) / 1e6, 1) if run_fd else None,
+                     "achieved_gbs_stagewise": round(fd_gbs, 1), "hbm_frac": round(fd_gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_node_step": 512},
+        "roofline": {"kernel": "fd_stage_kernel" if run_fd else "cs_step_kernel", "bound": "hbm",
+                     "achieved": round(fd_gbs if run_fd else cs_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round((fd_gbs if run_fd else cs_gbs) / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    if args.copy_calibration:
+        src = torch.empty(bytes_cs // 8, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 20
+        line["copy_calibration"] = {"bytes_moved": 2 * src.numel() * 4, "ms": round(ms, 5),
+                                    "gbs": round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(every)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -131,9 +131,27 @@ int lb_set_probe(lb_sim *sim, const double *ax, const double *ay, const double *
  * Returns LB_ENAN when a result is not finite. */
 int lb_reduce(lb_sim *sim, double out[5]);
 
-/* Run nsteps steps and record the diagnostics every `every` steps (at steps
- * 0, every, 2 every, ... <= nsteps) into series[(nsteps / every + 1) * 5],
- * fused into the step kernels where possible.  Synchronises. */
+/* Advance nsteps steps; for every step whose input state has
+ * lb_steps_done() % every == 0, the diagnostics of that input state are
+ * computed inside the step kernels (no extra pass over the state) and
+ * appended to the handle's series.  Asynchronous, like lb_step.  The series
+ * holds at most `capacity` samples (lb_series_reserve); further samples
+ * return LB_EBUSY before any step is launched. */
+int lb_step_sampled(lb_sim *sim, int nsteps, int every);
+
+/* Make room for `capacity` samples in the series (allocates; default 0). */
+int lb_series_reserve(lb_sim *sim, int capacity);
+
+/* Copy the pending samples as rows {t, M, Px, Py, E, A} (t = step index of
+ * the sampled state) into out[max_rows * 6], oldest first, and clear the
+ * series.  Synchronises.  Returns the number of rows copied (>= 0; samples
+ * beyond max_rows are dropped) or a negative LB_E* code. */
+int lb_series_read(lb_sim *sim, double *out, int max_rows);
+
+/* Run nsteps steps and return the diagnostics every `every` steps (at steps
+ * 0, every, 2 every, ... <= nsteps) in series[(nsteps / every + 1) * 5],
+ * fused into the step kernels except for a sample at t = nsteps.
+ * Synchronises; clears the handle's series. */
 int lb_run_sampled(lb_sim *sim, int nsteps, int every, double *series);
 
 /* Canonical (pre-collision) distribution f_k(x, t), [K][Ny][Nx] float64. */

@@ -15,8 +15,10 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+# -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
+# -ffp-contract=off: no automatic fusion of multiply-adds; the kernels write
+# their fmas explicitly, so every node evaluates the same rounded expression.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

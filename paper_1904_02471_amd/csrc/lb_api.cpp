@@ -58,6 +58,10 @@ struct lb_sim {
     double probe_den = 0.0;
     double *d_probe64 = nullptr;  // ax | ay | bx | by
     float *d_probe32 = nullptr;
+    double *d_series = nullptr;   // [series_cap][kDiag] raw sums
+    int series_cap = 0;
+    std::vector<long long> series_t;  // step index of each pending sample
+    std::vector<char> series_fused;   // sums in the step kernel's velocity unit
 };
 
 namespace {
@@ -350,6 +354,7 @@ void lb_destroy(lb_sim *s)
     if (s->d_out) (void)hipFree(s->d_out);
     if (s->d_probe64) (void)hipFree(s->d_probe64);
     if (s->d_probe32) (void)hipFree(s->d_probe32);
+    if (s->d_series) (void)hipFree(s->d_series);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
@@ -399,7 +404,8 @@ size_t lb_device_bytes(const lb_sim *s)
 {
     if (!s) return 0;
     return s->nbuf * s->buf_bytes + sizeof(double) * kDiag * ((size_t)s->partial_blocks + 1) +
-           (s->d_probe64 ? 2 * (s->Nx + s->Ny) * (sizeof(double) + sizeof(float)) : 0);
+           (s->d_probe64 ? 2 * (s->Nx + s->Ny) * (sizeof(double) + sizeof(float)) : 0) +
+           sizeof(double) * kDiag * (size_t)s->series_cap;
 }
 
 // Upload fields / state through a temporary device buffer.
@@ -618,49 +624,118 @@ int lb_reduce(lb_sim *s, double out[5])
     return LB_OK;
 }
 
-int lb_run_sampled(lb_sim *s, int nsteps, int every, double *series)
+int lb_series_reserve(lb_sim *s, int capacity)
 {
-    if (!s || nsteps < 0 || every < 1 || !series) return fail(LB_EINVAL);
-    if (!s->ready) return fail(LB_ESTATE);
-    const int nsamp = nsteps / every + 1;
-    double *d_series = nullptr;
-    if (hipMalloc(&d_series, sizeof(double) * kDiag * nsamp) != hipSuccess) {
+    if (!s || capacity < 0) return fail(LB_EINVAL);
+    if (capacity <= s->series_cap) return LB_OK;
+    double *d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * kDiag * (size_t)capacity) != hipSuccess) {
         (void)hipGetLastError();
         return fail(LB_ENOMEM);
     }
-    std::vector<int> fused(nsamp, 0);
     hipError_t e = hipSuccess;
-    for (int t = 0; t <= nsteps && e == hipSuccess; ++t) {
-        const bool sample = (t % every) == 0;
-        const int idx = t / every;
-        if (t == nsteps) {
-            if (sample)
-                e = with_type(s, [&](auto *tag) {
-                    using T = std::remove_pointer_t<decltype(tag)>;
-                    return reduce_into<T>(s, d_series + kDiag * idx);
-                });
-            break;
-        }
+    if (!s->series_t.empty())
+        e = hipMemcpyAsync(d, s->d_series, sizeof(double) * kDiag * s->series_t.size(), hipMemcpyDeviceToDevice,
+                           s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(dev_status(e));
+    }
+    if (s->d_series) (void)hipFree(s->d_series);
+    s->d_series = d;
+    s->series_cap = capacity;
+    return LB_OK;
+}
+
+// Steps with fused sampling: a step samples its input state when
+// (steps - base) % every == 0.
+static int sampled_steps(lb_sim *s, int nsteps, int every, long long base)
+{
+    long long need = 0;
+    for (long long t = s->steps; t < s->steps + nsteps; ++t)
+        if ((t - base) % every == 0) ++need;
+    if ((long long)s->series_t.size() + need > s->series_cap) return LB_EBUSY;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
+        const long long t = s->steps;
+        const bool sample = ((t - base) % every) == 0;
         e = with_type(s, [&](auto *tag) {
             using T = std::remove_pointer_t<decltype(tag)>;
             return step_once<T>(s, sample);
         });
         if (e == hipSuccess && sample) {
-            e = launch_diag_finalize(s->d_partial, diag_blocks_fused(s), d_series + kDiag * idx, s->stream);
-            fused[idx] = 1;
+            e = launch_diag_finalize(s->d_partial, diag_blocks_fused(s), s->d_series + kDiag * s->series_t.size(),
+                                     s->stream);
+            s->series_t.push_back(t);
+            s->series_fused.push_back(1);
         }
     }
-    std::vector<double> raw((size_t)kDiag * nsamp);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(raw.data(), d_series, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    return dev_status(e);
+}
+
+int lb_step_sampled(lb_sim *s, int nsteps, int every)
+{
+    if (!s || nsteps < 0 || every < 1) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    int rc = sampled_steps(s, nsteps, every, 0);
+    return rc == LB_OK ? LB_OK : fail(rc);
+}
+
+int lb_series_read(lb_sim *s, double *out, int max_rows)
+{
+    if (!s || (max_rows > 0 && !out) || max_rows < 0) return fail(LB_EINVAL);
+    const int n = (int)s->series_t.size();
+    std::vector<double> raw((size_t)kDiag * n);
+    hipError_t e = hipSuccess;
+    if (n > 0) e = hipMemcpyAsync(raw.data(), s->d_series, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(d_series);
     if (e != hipSuccess) return fail(dev_status(e));
-    // fused CS sums are in lattice velocity units (u / c_l); FD and the
-    // stand-alone reduction use physical velocities
-    for (int i = 0; i < nsamp; ++i)
-        finish_diag(s, raw.data() + kDiag * i, (fused[i] && s->cs) ? s->mi.cl : 1.0, series + kDiag * i);
-    if (!all_finite(series, (size_t)kDiag * nsamp)) return fail(LB_ENAN);
+    const int m = std::min(n, max_rows);
+    bool finite = true;
+    for (int i = 0; i < m; ++i) {
+        // fused CS sums are in lattice velocity units (u / c_l); FD and the
+        // stand-alone reduction use physical velocities
+        out[6 * i] = (double)s->series_t[i];
+        finish_diag(s, raw.data() + kDiag * i, (s->series_fused[i] && s->cs) ? s->mi.cl : 1.0, out + 6 * i + 1);
+        finite = finite && all_finite(out + 6 * i + 1, kDiag);
+    }
+    s->series_t.clear();
+    s->series_fused.clear();
+    if (!finite) return fail(LB_ENAN);
+    return m;
+}
+
+int lb_run_sampled(lb_sim *s, int nsteps, int every, double *series)
+{
+    if (!s || nsteps < 0 || every < 1 || !series) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    const int nsamp = nsteps / every + 1;
+    s->series_t.clear();
+    s->series_fused.clear();
+    int rc = lb_series_reserve(s, nsamp);
+    if (rc != LB_OK) return rc;
+    const long long base = s->steps;
+    rc = sampled_steps(s, nsteps, every, base);
+    if (rc == LB_OK && nsteps % every == 0) {
+        hipError_t e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return reduce_into<T>(s, s->d_series + kDiag * s->series_t.size());
+        });
+        s->series_t.push_back(s->steps);
+        s->series_fused.push_back(0);
+        rc = dev_status(e);
+    }
+    if (rc != LB_OK) {
+        s->series_t.clear();
+        s->series_fused.clear();
+        return fail(rc);
+    }
+    std::vector<double> rows((size_t)6 * nsamp);
+    const int got = lb_series_read(s, rows.data(), nsamp);
+    if (got < 0) return got;
+    for (int i = 0; i < got; ++i)
+        for (int j = 0; j < kDiag; ++j) series[kDiag * i + j] = rows[6 * i + 1 + j];
     return LB_OK;
 }
 

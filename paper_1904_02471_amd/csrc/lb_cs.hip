@@ -30,6 +30,9 @@ namespace {
 
 constexpr int kCsThreads = 256;
 
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T, bool FIXED, bool DIAG>
 __global__ __launch_bounds__(kCsThreads) void cs_step_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                              const Params<typename Arith<T>::type> p,
@@ -84,12 +87,12 @@ __global__ __launch_bounds__(kCsThreads) void cs_step_kernel(const T *__restrict
         const CT jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
         const CT inv = CT(1) / rho;
         const CT ux = jx * inv, uy = jy * inv;
-        const CT usq = c15 * (ux * ux + uy * uy);
+        const CT usq = c15 * fmaT(ux, ux, uy * uy);
 
         // second-order equilibrium, shifted: w_k [drho + rho (3 eu + 4.5 eu^2 - 1.5 u^2)]
         auto relax = [&](CT g, CT w, CT eu) -> CT {
-            const CT geq = w * (drho + rho * (eu * (c3 + c45 * eu) - usq));
-            return g + omega * (geq - g);
+            const CT geq = w * fmaT(rho, fmaT(eu, fmaT(c45, eu, c3), -usq), drho);
+            return fmaT(omega, geq - g, g);
         };
         store_from(o + x, relax(g0, w0, CT(0)));
         store_from(o + 1 * P + x, relax(g1, w1, ux));

@@ -35,6 +35,8 @@ constexpr int kLoadsPerThread = (kTileElems + kFdThreads - 1) / kFdThreads;
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // WENO-5 (Jiang-Shu) interface value downstream of cell c from the values
 // a, b, c, d, e ordered along the upwind direction.  The nonlinear weights
@@ -42,22 +44,26 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 // denominator so that one reciprocal serves the interface:
 //   omega_0 : omega_1 : omega_2 = 0.1 s1 s2 : 0.6 s0 s2 : 0.3 s0 s1,
 //   s_r = (eps + beta_r)^2.
+// Every multiply-add is an explicit fma (the library is compiled without
+// automatic contraction), so each interface is the same function of its five
+// inputs wherever it is evaluated: a uniform state stays uniform to the bit.
 template <typename CT>
 __device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
 {
     const CT k13 = CT(13.0 / 12.0), q = CT(0.25);
-    const CT t0 = a - CT(2) * b + c, u0 = a - CT(4) * b + CT(3) * c;
-    const CT t1 = b - CT(2) * c + d, u1 = b - d;
-    const CT t2 = c - CT(2) * d + e, u2 = CT(3) * c - CT(4) * d + e;
-    const CT s0 = eps + (k13 * t0 * t0 + q * u0 * u0);
-    const CT s1 = eps + (k13 * t1 * t1 + q * u1 * u1);
-    const CT s2 = eps + (k13 * t2 * t2 + q * u2 * u2);
+    const CT t0 = fmaT(CT(-2), b, a + c), u0 = fmaT(CT(-4), b, fmaT(CT(3), c, a));
+    const CT t1 = fmaT(CT(-2), c, b + d), u1 = b - d;
+    const CT t2 = fmaT(CT(-2), d, c + e), u2 = fmaT(CT(3), c, fmaT(CT(-4), d, e));
+    const CT s0 = fmaT(k13 * t0, t0, fmaT(q * u0, u0, eps));
+    const CT s1 = fmaT(k13 * t1, t1, fmaT(q * u1, u1, eps));
+    const CT s2 = fmaT(k13 * t2, t2, fmaT(q * u2, u2, eps));
     const CT S0 = s0 * s0, S1 = s1 * s1, S2 = s2 * s2;
     const CT a0 = CT(0.1) * (S1 * S2), a1 = CT(0.6) * (S0 * S2), a2 = CT(0.3) * (S0 * S1);
-    const CT q0 = CT(2) * a - CT(7) * b + CT(11) * c;
-    const CT q1 = -b + CT(5) * c + CT(2) * d;
-    const CT q2 = CT(2) * c + CT(5) * d - e;
-    return (a0 * q0 + a1 * q1 + a2 * q2) * fast_rcp(CT(6) * (a0 + a1 + a2));
+    const CT q0 = fmaT(CT(11), c, fmaT(CT(-7), b, CT(2) * a));
+    const CT q1 = fmaT(CT(5), c, fmaT(CT(2), d, -b));
+    const CT q2 = fmaT(CT(5), d, fmaT(CT(2), c, -e));
+    const CT num = fmaT(a0, q0, fmaT(a1, q1, a2 * q2));
+    return num * fast_rcp(CT(6) * ((a0 + a1) + a2));
 }
 
 __device__ __forceinline__ int wrap(int v, int n)
@@ -127,8 +133,8 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
             for (int r = 0; r < kRows; ++r) {
                 const CT g = ld(sk + noff[r]);
                 dr[r] += g;
-                jx[r] += g * vxk;
-                jy[r] += g * vyk;
+                jx[r] = fmaT(g, vxk, jx[r]);
+                jy[r] = fmaT(g, vyk, jy[r]);
             }
         }
         DiagAcc acc;
@@ -237,15 +243,16 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
             CT cpre[N + 1];
             cpre[0] = CT(0);
 #pragma unroll
-            for (int m = 1; m <= N; ++m) cpre[m] = cpre[m - 1] + p.hc[qj][m] * pyn[r][m];
+            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(p.hc[qj][m], pyn[r][m], cpre[m - 1]);
             CT pp = cpre[N];
 #pragma unroll
-            for (int n = 1; n <= N; ++n) pp += (p.hc[qi][n] * pxn[r][n]) * (CT(1) + cpre[N - n]);
-            const CT geq = p.w[k] * (drho[r] + rho[r] * pp);
+            for (int n = 1; n <= N; ++n) pp = fmaT(p.hc[qi][n] * pxn[r][n], CT(1) + cpre[N - n], pp);
+            const CT geq = p.w[k] * fmaT(rho[r], pp, drho[r]);
 
-            const CT L = -(vxk * dfx + vyk * dfy[r]) * inv_ds - (g - geq) * inv_tau;
-            CT res = g + dt * L;
-            if (gn) res = ca * gnv[r] + cb * res;
+            const CT adv = fmaT(vxk, dfx, vyk * dfy[r]) * inv_ds;
+            const CT L = -fmaT(g - geq, inv_tau, adv);
+            CT res = fmaT(dt, L, g);
+            if (gn) res = fmaT(ca, gnv[r], cb * res);
             if (active[r]) store_from(out + k * P + noff[r], res);
         }
     }

@@ -20,6 +20,7 @@ Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_F
 # every symbol include/lb.h declares (checked by the CPU test-suite)
 EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
            "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_run_sampled",
+           "lb_step_sampled", "lb_series_reserve", "lb_series_read",
            "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_stream", "lb_synchronize", "lb_device_bytes"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -51,6 +52,9 @@ def _load():
         "lb_set_probe": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
         "lb_reduce": (ctypes.c_int, [_vp, _dp]),
         "lb_run_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
+        "lb_step_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+        "lb_series_reserve": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_series_read": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
         "lb_get_state": (ctypes.c_int, [_vp, _dp]),
         "lb_set_state": (ctypes.c_int, [_vp, _dp]),
         "lb_steps_done": (ctypes.c_longlong, [_vp]),
@@ -163,9 +167,23 @@ class Sim:
         return out
 
     def run_sampled(self, nsteps, every):
-        out = np.empty((int(nsteps) // int(every) + 1, 5))
+        n = int(nsteps) // int(every) + 1 if int(every) > 0 and int(nsteps) >= 0 else 1
+        out = np.empty((n, 5))
         _check(_lib.lb_run_sampled(self._h, int(nsteps), int(every), _ptr(out)), "lb_run_sampled")
         return out
+
+    def step_sampled(self, nsteps, every):
+        _check(_lib.lb_step_sampled(self._h, int(nsteps), int(every)), "lb_step_sampled")
+
+    def series_reserve(self, capacity):
+        _check(_lib.lb_series_reserve(self._h, int(capacity)), "lb_series_reserve")
+
+    def series_read(self, max_rows=1 << 16):
+        out = np.empty((int(max_rows), 6))
+        n = _lib.lb_series_read(self._h, _ptr(out), int(max_rows))
+        if n < 0:
+            raise LBError(n, "lb_series_read")
+        return out[:n].copy()
 
     def get_state(self):
         f = np.empty((self.K, self.Ny, self.Nx))
@@ -229,6 +247,18 @@ def lb_reduce(sim):
 
 def lb_run_sampled(sim, nsteps, every):
     return sim.run_sampled(nsteps, every)
+
+
+def lb_step_sampled(sim, nsteps, every):
+    sim.step_sampled(nsteps, every)
+
+
+def lb_series_reserve(sim, capacity):
+    sim.series_reserve(capacity)
+
+
+def lb_series_read(sim, max_rows=1 << 16):
+    return sim.series_read(max_rows)
 
 
 def lb_get_state(sim):

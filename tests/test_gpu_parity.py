@@ -271,3 +271,25 @@ def test_error_paths():
     with pytest.raises(lb.LBError):
         g.run_sampled(10, 0)
     assert g.device_bytes() >= 2 * 9 * 64 * 4
+
+
+def test_step_sampled_series():
+    print("case: step_sampled series", flush=True)
+    g = lb.Sim(lb.LB_CS_D2Q9, 48, 32, 0.6, 1.0, 1.0, 2, precision=lb.LB_FP64)
+    o = lb.Sim(lb.LB_CS_D2Q9, 48, 32, 0.6, 1.0, 1.0, 2, precision=lb.LB_FP64)
+    rho, ux, uy, _ = workloads.taylor_green(48, 32, 0.02, 1.0 / 3.0)
+    ax, ay, bx, by = workloads.separable_pattern("tgv", 48, 32)
+    for s in (g, o):
+        s.init(rho, ux, uy)
+        s.set_probe(ax, ay, bx, by)
+    with pytest.raises(lb.LBError) as e:
+        g.step_sampled(5, 5)               # no capacity reserved
+    assert e.value.code == lb.LB_EBUSY
+    g.series_reserve(8)
+    g.step_sampled(7, 5)                   # samples t = 0, 5
+    g.step_sampled(6, 5)                   # samples t = 10
+    rows = g.series_read()
+    assert [int(t) for t in rows[:, 0]] == [0, 5, 10]
+    ref = o.run_sampled(10, 5)
+    np.testing.assert_allclose(rows[:, 1:], ref, rtol=1e-12, atol=1e-15 * ref[0, 0])
+    assert g.series_read().shape == (0, 6)
