@@ -105,7 +105,10 @@ int lb_model_info(int model, double ds, double dt, double *vx, double *vy, doubl
  * Must be called before lb_init / lb_set_state.  Densities must be > 0. */
 int lb_set_bc_x(lb_sim *sim, double rho_left, double rho_right);
 
-/* FD only: tolerance eps of the WENO-5 nonlinear weights (default 1e-6). */
+/* FD only: tolerance eps of the WENO-5 nonlinear weights (default 1e-6;
+ * the weights of Jiang and Shu, the paper's WENO-5 reference, Section 2).
+ * Accepted range: [1e-9, 1e9] with FP32 arithmetic, [1e-75, 1e75] with FP64
+ * (the weights are formed from (eps + beta)^4); LB_EINVAL otherwise. */
 int lb_set_weno_eps(lb_sim *sim, double eps);
 
 /* f := f_eq(rho, u) at every node (rho > 0).  Sets rho0 to the mean of rho

@@ -379,6 +379,9 @@ int lb_set_weno_eps(lb_sim *s, double eps)
 {
     if (!s || !(eps > 0) || !std::isfinite(eps)) return fail(LB_EINVAL);
     if (s->cs) return fail(LB_EINVAL);
+    // the WENO weights use (eps + beta)^4, which must stay a normal number
+    const double lo = s->prec == P64 ? 1e-75 : 1e-9, hi = s->prec == P64 ? 1e75 : 1e9;
+    if (eps < lo || eps > hi) return fail(LB_EINVAL);
     s->eps = eps;
     return LB_OK;
 }

@@ -3,21 +3,37 @@
 //
 //   L(g)_k = -[v_kx (F_{i+1/2} - F_{i-1/2}) + v_ky (G_{j+1/2} - G_{j-1/2})] / ds
 //            - (g_k - g_eq_k(g)) / tau
-//   stage 1: A   = g   + dt L(g)
-//   stage 2: B   = 3/4 g + 1/4 (A + dt L(A))
-//   stage 3: g' = 1/3 g + 2/3 (B + dt L(B))      (written over g)
+//   stage 1: A  = g + dt L(g)
+//   stage 2: B  = g + 1/4 (A + dt L(A) - g)           (= 3/4 g + 1/4 (A + dt L(A)))
+//   stage 3: g' = g + 2/3 (B + dt L(B) - g)           (= 1/3 g + 2/3 (B + dt L(B)))
 //
 // with F, G the WENO-5 reconstructions on the upwind side of each interface
-// and g_eq the Hermite equilibrium of order N (Section 1).
+// and g_eq the Hermite equilibrium of order N (Section 1).  The combinations
+// are written as g + c (x - g) so that the two weights sum to one exactly in
+// floating point (1/3 and 2/3 do not): no spurious growth of the state.
 //
-// Mapping: a workgroup of 256 threads owns a 64 x 16 tile; thread (lx, wy)
-// owns column lx and rows 4 wy .. 4 wy + 3.  The workgroup first gathers the
-// moments of its nodes (K loads per node), then loops over the populations:
-// the tile of population k plus a 3-node halo is staged in LDS, each thread
-// computes the x and y flux differences of its 4 nodes, the equilibrium of
-// population k from the node's moments (kept in registers), and writes the
-// Runge-Kutta combination.  Only O(N) registers per node are live across the
-// population loop, so the same kernel serves K = 9 .. 36.
+// The stage is bound by vector-ALU issue (WENO-5 costs ~45 instructions per
+// face), so the mapping is chosen to evaluate every face once and to share
+// work between neighbouring faces:
+//
+//   A workgroup of 256 threads owns a 64 x 16 tile; thread (lx, wy) owns
+//   column lx and the 4 rows 4 wy .. 4 wy + 3.
+//   1. moments: the thread gathers the K values of its 4 nodes and keeps
+//      rho, drho and the powers of u (2 + 2N registers per node).
+//   2. loop over the populations k; the tile of population k with a 3-node
+//      halo is staged in LDS (double-buffered; the next tile is prefetched
+//      into registers while the current one is used):
+//      a. x-faces: lane lx reconstructs the right face of each of its 4
+//         nodes (the 64 lanes of a wave cover a row), and 16 lanes of wave 0
+//         the left face of column 0 of the 16 rows; faces go to LDS;
+//      b. y-faces: the thread marches up its column, 5 faces for its 4
+//         nodes, keeping a 9-value window in registers so that the second
+//         differences and their smoothness terms are computed once and
+//         shared by the three faces that use them;
+//      c. node update: flux differences, order-N equilibrium of population
+//         k from the moment registers, Runge-Kutta combination, store.
+//   The sign of v_kx / v_ky is uniform over the launch, so the upwind side
+//   is a scalar branch and every LDS access has a constant offset.
 #include "lb_diag.h"
 #include "lb_internal.h"
 
@@ -32,6 +48,7 @@ constexpr int kLX = kTX + 2 * kHalo;  // 70
 constexpr int kLY = kTY + 2 * kHalo;  // 22
 constexpr int kTileElems = kLX * kLY;
 constexpr int kLoadsPerThread = (kTileElems + kFdThreads - 1) / kFdThreads;
+constexpr int kXFaceStride = kTX + 1;  // x-faces per tile row
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
@@ -39,31 +56,51 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // WENO-5 (Jiang-Shu) interface value downstream of cell c from the values
-// a, b, c, d, e ordered along the upwind direction.  The nonlinear weights
-// alpha_r = d_r / (eps + beta_r)^2, normalised, are formed over a common
-// denominator so that one reciprocal serves the interface:
-//   omega_0 : omega_1 : omega_2 = 0.1 s1 s2 : 0.6 s0 s2 : 0.3 s0 s1,
-//   s_r = (eps + beta_r)^2.
+// a, b, c, d, e ordered along the upwind direction:
+//   candidates q0 = (2a - 7b + 11c)/6, q1 = (-b + 5c + 2d)/6, q2 = (2c + 5d - e)/6
+//   smoothness beta0 = 13/12 (a-2b+c)^2 + 1/4 (a-4b+3c)^2,
+//              beta1 = 13/12 (b-2c+d)^2 + 1/4 (b-d)^2,
+//              beta2 = 13/12 (c-2d+e)^2 + 1/4 (3c-4d+e)^2
+//   weights    alpha_r = d_r / (eps + beta_r)^2, d = (0.1, 0.6, 0.3)
+//   value      sum alpha_r q_r / sum alpha_r.
+// The weights are formed over the common denominator (eps+beta0)^2
+// (eps+beta1)^2 (eps+beta2)^2, so one reciprocal serves the interface; the
+// linear weights and the 1/6 are folded into the candidate coefficients.
+// eps + 13/12 (second difference)^2 is formed first: when faces are
+// evaluated in a row, these terms are common subexpressions of neighbouring
+// faces.  FP32 range: (eps + beta)^4 must stay a normal number, hence the
+// library accepts 1e-9 <= eps <= 1e9 for FP32 arithmetic.
 // Every multiply-add is an explicit fma (the library is compiled without
-// automatic contraction), so each interface is the same function of its five
-// inputs wherever it is evaluated: a uniform state stays uniform to the bit.
+// automatic contraction), so an interface is the same function of its five
+// inputs wherever it is evaluated.
 template <typename CT>
 __device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
 {
     const CT k13 = CT(13.0 / 12.0), q = CT(0.25);
-    const CT t0 = fmaT(CT(-2), b, a + c), u0 = fmaT(CT(-4), b, fmaT(CT(3), c, a));
+    const CT t0 = fmaT(CT(-2), b, a + c), u0 = fmaT(CT(2), c - b, t0);
     const CT t1 = fmaT(CT(-2), c, b + d), u1 = b - d;
-    const CT t2 = fmaT(CT(-2), d, c + e), u2 = fmaT(CT(3), c, fmaT(CT(-4), d, e));
-    const CT s0 = fmaT(k13 * t0, t0, fmaT(q * u0, u0, eps));
-    const CT s1 = fmaT(k13 * t1, t1, fmaT(q * u1, u1, eps));
-    const CT s2 = fmaT(k13 * t2, t2, fmaT(q * u2, u2, eps));
+    const CT t2 = fmaT(CT(-2), d, c + e), u2 = fmaT(CT(2), c - d, t2);
+    const CT s0 = fmaT(q * u0, u0, fmaT(k13 * t0, t0, eps));
+    const CT s1 = fmaT(q * u1, u1, fmaT(k13 * t1, t1, eps));
+    const CT s2 = fmaT(q * u2, u2, fmaT(k13 * t2, t2, eps));
     const CT S0 = s0 * s0, S1 = s1 * s1, S2 = s2 * s2;
-    const CT a0 = CT(0.1) * (S1 * S2), a1 = CT(0.6) * (S0 * S2), a2 = CT(0.3) * (S0 * S1);
-    const CT q0 = fmaT(CT(11), c, fmaT(CT(-7), b, CT(2) * a));
-    const CT q1 = fmaT(CT(5), c, fmaT(CT(2), d, -b));
-    const CT q2 = fmaT(CT(5), d, fmaT(CT(2), c, -e));
-    const CT num = fmaT(a0, q0, fmaT(a1, q1, a2 * q2));
-    return num * fast_rcp(CT(6) * ((a0 + a1) + a2));
+    const CT A0 = S1 * S2, A1 = S0 * S2, A2 = S0 * S1;
+    // (d_r / 6) * candidate polynomials
+    const CT Q0 = fmaT(CT(11.0 / 60.0), c, fmaT(CT(-7.0 / 60.0), b, CT(1.0 / 30.0) * a));
+    const CT Q1 = fmaT(CT(0.5), c, fmaT(CT(0.2), d, CT(-0.1) * b));
+    const CT Q2 = fmaT(CT(0.25), d, fmaT(CT(0.1), c, CT(-0.05) * e));
+    const CT num = fmaT(A0, Q0, fmaT(A1, Q1, A2 * Q2));
+    const CT den = fmaT(CT(0.1), A0, fmaT(CT(0.6), A1, CT(0.3) * A2));
+    return num * fast_rcp(den);
+}
+
+// Face between LDS cells i and i + s (s = 1 along x, kLX along y); the
+// upwind side follows the sign of the velocity component.
+template <typename CT>
+__device__ __forceinline__ CT face_at(const CT *L, int i, int s, bool positive, CT eps)
+{
+    if (positive) return weno5(L[i - 2 * s], L[i - s], L[i], L[i + s], L[i + 2 * s], eps);
+    return weno5(L[i + 3 * s], L[i + 2 * s], L[i + s], L[i], L[i - s], eps);
 }
 
 __device__ __forceinline__ int wrap(int v, int n)
@@ -72,15 +109,15 @@ __device__ __forceinline__ int wrap(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-template <typename T, int N, bool FIXED, bool DIAG>
+template <typename T, int N, bool FIXED, bool DIAG, bool WITH_GN>
 __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
-                                                              const typename Arith<T>::type ca,
                                                               const typename Arith<T>::type cb,
                                                               const Params<typename Arith<T>::type> p,
                                                               const DiagArgs<typename Arith<T>::type> d)
 {
     using CT = typename Arith<T>::type;
-    __shared__ CT tile[kLY][kLX];
+    __shared__ CT tile[2][kTileElems];
+    __shared__ CT xface[kTY * kXFaceStride];
 
     const int tid = threadIdx.x;
     const int lx = tid & 63, wy = tid >> 6;
@@ -89,7 +126,8 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
     const long long P = p.plane;
 
     // --- offsets of the tile elements this thread stages (fixed over k) ---
-    // code: >= 0 element offset inside a plane, -1 left end, -2 right end, -3 unused
+    // >= 0: element offset inside a plane; -1 / -2: left / right end state;
+    // -3: no element
     int toff[kLoadsPerThread];
 #pragma unroll
     for (int i = 0; i < kLoadsPerThread; ++i) {
@@ -98,17 +136,34 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
             const int r = e / kLX, c = e - r * kLX;
             const int gy = wrap(y0 - kHalo + r, Ny);
             const int gxr = x0 - kHalo + c;
-            if (FIXED && gxr < 0) {
+            if (FIXED && gxr < 0)
                 toff[i] = -1;
-            } else if (FIXED && gxr >= Nx) {
+            else if (FIXED && gxr >= Nx)
                 toff[i] = -2;
-            } else {
+            else
                 toff[i] = gy * p.pitch + p.xoff + wrap(gxr, Nx);
-            }
         } else {
             toff[i] = -3;
         }
     }
+    auto fetch = [&](int k, CT *reg) {
+        const T *sk = src + k * P;
+#pragma unroll
+        for (int i = 0; i < kLoadsPerThread; ++i) {
+            const int o = toff[i];
+            if (o >= 0)
+                reg[i] = ld(sk + o);
+            else if (FIXED && o == -1)
+                reg[i] = p.ghost_l[k];
+            else if (FIXED && o == -2)
+                reg[i] = p.ghost_r[k];
+        }
+    };
+    auto stash = [&](int buf, const CT *reg) {
+#pragma unroll
+        for (int i = 0; i < kLoadsPerThread; ++i)
+            if (toff[i] != -3) tile[buf][tid + i * kFdThreads] = reg[i];
+    };
 
     // --- moments of the thread's nodes ---
     const int gx = x0 + lx;
@@ -122,10 +177,13 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
         active[r] = colok && gy < Ny;
         noff[r] = (gy < Ny ? gy : Ny - 1) * p.pitch + p.xoff + (colok ? gx : Nx - 1);
     }
+    CT pre[kLoadsPerThread];
+    fetch(0, pre);
     {
         CT dr[kRows], jx[kRows], jy[kRows];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) dr[r] = jx[r] = jy[r] = CT(0);
+#pragma unroll 4
         for (int k = 0; k < p.K; ++k) {
             const CT vxk = p.vx[k], vyk = p.vy[k];
             const T *sk = src + k * P;
@@ -160,58 +218,57 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
                 acc.v[0] += (double)dr[r];
                 acc.v[1] += (double)jx[r];
                 acc.v[2] += (double)jy[r];
-                acc.v[3] += (double)(CT(0.5) * rho[r] * (ux * ux + uy * uy));
-                if (d.ax) acc.v[4] += (double)(ux * (pax * d.ay[gy]) + uy * (pbx * d.by[gy]));
+                acc.v[3] += (double)(CT(0.5) * rho[r] * fmaT(ux, ux, uy * uy));
+                if (d.ax) acc.v[4] += (double)fmaT(ux, pax * d.ay[gy], uy * (pbx * d.by[gy]));
             }
         }
         if (DIAG) block_diag_store(acc, d.partial, blockIdx.y * gridDim.x + blockIdx.x);
     }
 
-    const CT eps = p.eps, inv_ds = p.inv_ds, inv_tau = p.inv_tau, dt = p.dt;
-    const int lc = lx + kHalo;  // LDS column of the thread's nodes
+    const CT eps = p.eps, dt = p.dt, inv_tau = p.inv_tau;
+    stash(0, pre);
+    if (p.K > 1) fetch(1, pre);
+    __syncthreads();
+
+    const int c0 = (wy * kRows + kHalo) * kLX + lx + kHalo;  // LDS cell of the thread's first node
 
     for (int k = 0; k < p.K; ++k) {
-        __syncthreads();  // previous population's tile fully consumed
-        const T *sk = src + k * P;
-#pragma unroll
-        for (int i = 0; i < kLoadsPerThread; ++i) {
-            const int e = tid + i * kFdThreads;
-            if (e < kTileElems) {
-                const int o = toff[i];
-                CT v;
-                if (FIXED && o == -1)
-                    v = p.ghost_l[k];
-                else if (FIXED && o == -2)
-                    v = p.ghost_r[k];
-                else
-                    v = ld(sk + o);
-                (&tile[0][0])[e] = v;
-            }
-        }
+        const int buf = k & 1;
+        const CT *L = tile[buf];
+        const CT vxk = p.vx[k], vyk = p.vy[k];
+        const bool xpos = vxk > CT(0), ypos = vyk > CT(0);
+
         CT gnv[kRows];
-        if (gn) {
+        if (WITH_GN) {
             const T *gk = gn + k * P;
 #pragma unroll
             for (int r = 0; r < kRows; ++r) gnv[r] = ld(gk + noff[r]);
         }
-        __syncthreads();
 
-        const CT vxk = p.vx[k], vyk = p.vy[k];
-        const int qi = p.ki[k], qj = p.kj[k];
+        // a. x-faces: right face of each node; left face of column 0 by 16 lanes
+        CT fr[kRows];
+        if (vxk != CT(0)) {
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                fr[r] = face_at(L, c0 + r * kLX, 1, xpos, eps);
+                xface[(wy * kRows + r) * kXFaceStride + lx + 1] = fr[r];
+            }
+            if (wy == 0 && lx < kTY)
+                xface[lx * kXFaceStride] = face_at(L, (lx + kHalo) * kLX + kHalo - 1, 1, xpos, eps);
+        }
 
-        // y flux differences: march up the column, 5 interfaces for 4 nodes
+        // b. y-faces: march up the column, 5 faces for the 4 nodes
         CT dfy[kRows];
         if (vyk != CT(0)) {
-            const int rb = wy * kRows + kHalo;  // LDS row of the first node
+            CT w[9];
+            const int wb = c0 + (ypos ? -3 : -2) * kLX;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) w[i] = L[wb + i * kLX];
             CT prev = CT(0);
 #pragma unroll
             for (int m = 0; m <= kRows; ++m) {
-                const int c = rb - 1 + m;  // interface between rows c and c+1
-                CT G;
-                if (vyk > CT(0))
-                    G = weno5(tile[c - 2][lc], tile[c - 1][lc], tile[c][lc], tile[c + 1][lc], tile[c + 2][lc], eps);
-                else
-                    G = weno5(tile[c + 3][lc], tile[c + 2][lc], tile[c + 1][lc], tile[c][lc], tile[c - 1][lc], eps);
+                const CT G = ypos ? weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps)
+                                  : weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
                 if (m > 0) dfy[m - 1] = G - prev;
                 prev = G;
             }
@@ -219,22 +276,22 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
 #pragma unroll
             for (int r = 0; r < kRows; ++r) dfy[r] = CT(0);
         }
+        __syncthreads();
 
+        // c. node updates
+        const int qi = p.ki[k], qj = p.kj[k];
+        const CT wk = p.w[k];
+        const CT vxs = vxk * p.inv_ds, vys = vyk * p.inv_ds;
+        CT hx[N + 1], hy[N + 1];
+#pragma unroll
+        for (int n = 1; n <= N; ++n) {
+            hx[n] = p.hc[qi][n];
+            hy[n] = p.hc[qj][n];
+        }
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            const int lr = wy * kRows + r + kHalo;
-            const CT *row = tile[lr];
-            CT dfx = CT(0);
-            if (vxk > CT(0)) {
-                const CT fr = weno5(row[lc - 2], row[lc - 1], row[lc], row[lc + 1], row[lc + 2], eps);
-                const CT fl = weno5(row[lc - 3], row[lc - 2], row[lc - 1], row[lc], row[lc + 1], eps);
-                dfx = fr - fl;
-            } else if (vxk < CT(0)) {
-                const CT fr = weno5(row[lc + 3], row[lc + 2], row[lc + 1], row[lc], row[lc - 1], eps);
-                const CT fl = weno5(row[lc + 2], row[lc + 1], row[lc], row[lc - 1], row[lc - 2], eps);
-                dfx = fr - fl;
-            }
-            const CT g = row[lc];
+            const CT g = L[c0 + r * kLX];
+            const CT dfx = (vxk != CT(0)) ? fr[r] - xface[(wy * kRows + r) * kXFaceStride + lx] : CT(0);
 
             // order-N equilibrium, shifted:  w_k [drho + rho P'(u)],
             // P' = sum_{1 <= n+m <= N} a_n b_m with a_n = He_n(xi_i) ux^n / n!,
@@ -243,18 +300,25 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
             CT cpre[N + 1];
             cpre[0] = CT(0);
 #pragma unroll
-            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(p.hc[qj][m], pyn[r][m], cpre[m - 1]);
+            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(hy[m], pyn[r][m], cpre[m - 1]);
             CT pp = cpre[N];
 #pragma unroll
-            for (int n = 1; n <= N; ++n) pp = fmaT(p.hc[qi][n] * pxn[r][n], CT(1) + cpre[N - n], pp);
-            const CT geq = p.w[k] * fmaT(rho[r], pp, drho[r]);
+            for (int n = 1; n <= N; ++n) pp = fmaT(hx[n] * pxn[r][n], CT(1) + cpre[N - n], pp);
+            const CT geq = wk * fmaT(rho[r], pp, drho[r]);
 
-            const CT adv = fmaT(vxk, dfx, vyk * dfy[r]) * inv_ds;
-            const CT L = -fmaT(g - geq, inv_tau, adv);
-            CT res = fmaT(dt, L, g);
-            if (gn) res = fmaT(ca, gnv[r], cb * res);
+            const CT adv = fmaT(vxs, dfx, vys * dfy[r]);
+            const CT Lk = -fmaT(g - geq, inv_tau, adv);
+            CT res = fmaT(dt, Lk, g);
+            if (WITH_GN) res = fmaT(cb, res - gnv[r], gnv[r]);
             if (active[r]) store_from(out + k * P + noff[r], res);
         }
+
+        // d. next tile into the other LDS buffer, prefetch the one after
+        if (k + 1 < p.K) {
+            stash(buf ^ 1, pre);
+            if (k + 2 < p.K) fetch(k + 2, pre);
+        }
+        __syncthreads();
     }
 }
 
@@ -264,22 +328,18 @@ hipError_t launch_fd_n(const T *src, const T *gn, T *out, int stage, const Param
 {
     using CT = typename Arith<T>::type;
     dim3 grid((p.Nx + kTX - 1) / kTX, (p.Ny + kTY - 1) / kTY), block(kFdThreads);
-    CT ca = CT(0), cb = CT(1);
-    const T *g = nullptr;
-    if (stage == 2) {
-        ca = CT(0.75);
-        cb = CT(0.25);
-        g = gn;
-    } else if (stage == 3) {
-        ca = CT(1) / CT(3);
-        cb = CT(2) / CT(3);
-        g = gn;
-    }
-    if (diag && stage == 1) {
-        hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, true>), grid, block, 0, s, src, g, out, ca, cb, p, *diag);
+    DiagArgs<CT> none{};
+    if (stage == 1) {
+        if (diag)
+            hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, true, false>), grid, block, 0, s, src, nullptr, out,
+                               CT(1), p, *diag);
+        else
+            hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false, false>), grid, block, 0, s, src, nullptr, out,
+                               CT(1), p, none);
     } else {
-        DiagArgs<CT> none{};
-        hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false>), grid, block, 0, s, src, g, out, ca, cb, p, none);
+        const CT cb = (stage == 2) ? CT(0.25) : CT(2) / CT(3);
+        hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false, true>), grid, block, 0, s, src, gn, out, cb, p,
+                           none);
     }
     return hipGetLastError();
 }
