@@ -12,28 +12,29 @@
 // are written as g + c (x - g) so that the two weights sum to one exactly in
 // floating point (1/3 and 2/3 do not): no spurious growth of the state.
 //
-// The stage is bound by vector-ALU issue (WENO-5 costs ~45 instructions per
-// face), so the mapping is chosen to evaluate every face once and to share
-// work between neighbouring faces:
+// The stage is bound by vector-ALU issue (the WENO-5 face is the bulk of the
+// work), so the mapping evaluates every face once and marches along rows and
+// columns so that neighbouring faces share their differences and smoothness
+// terms:
 //
-//   A workgroup of 256 threads owns a 64 x 16 tile; thread (lx, wy) owns
-//   column lx and the 4 rows 4 wy .. 4 wy + 3.
-//   1. moments: the thread gathers the K values of its 4 nodes and keeps
-//      rho, drho and the powers of u (2 + 2N registers per node).
+//   A workgroup of 256 threads owns a 64 x 32 tile; thread (lx, wy) owns
+//   column lx and the 8 rows 8 wy .. 8 wy + 7.
+//   1. moments: the thread gathers the K values of its 8 nodes and keeps
+//      drho, u_x, u_y per node.
 //   2. loop over the populations k; the tile of population k with a 3-node
 //      halo is staged in LDS (double-buffered; the next tile is prefetched
 //      into registers while the current one is used):
-//      a. x-faces: lane lx reconstructs the right face of each of its 4
-//         nodes (the 64 lanes of a wave cover a row), and 16 lanes of wave 0
-//         the left face of column 0 of the 16 rows; faces go to LDS;
-//      b. y-faces: the thread marches up its column, 5 faces for its 4
-//         nodes, keeping a 9-value window in registers so that the second
-//         differences and their smoothness terms are computed once and
-//         shared by the three faces that use them;
+//      a. x-faces: thread (row tid / 8, segment tid % 8) marches along its
+//         row over 8 faces from a 12-value register window; 32 lanes add the
+//         left face of column 0 of the 32 rows; faces go to LDS;
+//      b. y-faces: thread (lx, wy) marches up its column, 9 faces for its 8
+//         nodes, from a 13-value register window, in registers;
 //      c. node update: flux differences, order-N equilibrium of population
-//         k from the moment registers, Runge-Kutta combination, store.
+//         k, Runge-Kutta combination, store.
 //   The sign of v_kx / v_ky is uniform over the launch, so the upwind side
 //   is a scalar branch and every LDS access has a constant offset.
+#include <type_traits>
+
 #include "lb_diag.h"
 #include "lb_internal.h"
 
@@ -41,14 +42,17 @@ namespace lbm {
 
 namespace {
 
-constexpr int kTX = 64, kTY = 16, kRows = 4;
+constexpr int kTX = 64, kTY = 32, kRows = 8;
 constexpr int kFdThreads = 256;
 constexpr int kHalo = 3;
 constexpr int kLX = kTX + 2 * kHalo;  // 70
-constexpr int kLY = kTY + 2 * kHalo;  // 22
+constexpr int kLY = kTY + 2 * kHalo;  // 38
 constexpr int kTileElems = kLX * kLY;
 constexpr int kLoadsPerThread = (kTileElems + kFdThreads - 1) / kFdThreads;
 constexpr int kXFaceStride = kTX + 1;  // x-faces per tile row
+constexpr int kSeg = 8;                // x-faces per marching segment
+static_assert(kTY * (kTX / kSeg) == kFdThreads, "one x-face segment per thread");
+static_assert(kTY <= 64, "the column-0 faces are computed by one wave");
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
@@ -63,44 +67,38 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 //              beta2 = 13/12 (c-2d+e)^2 + 1/4 (3c-4d+e)^2
 //   weights    alpha_r = d_r / (eps + beta_r)^2, d = (0.1, 0.6, 0.3)
 //   value      sum alpha_r q_r / sum alpha_r.
-// The weights are formed over the common denominator (eps+beta0)^2
-// (eps+beta1)^2 (eps+beta2)^2, so one reciprocal serves the interface; the
-// linear weights and the 1/6 are folded into the candidate coefficients.
-// eps + 13/12 (second difference)^2 is formed first: when faces are
-// evaluated in a row, these terms are common subexpressions of neighbouring
-// faces.  FP32 range: (eps + beta)^4 must stay a normal number, hence the
-// library accepts 1e-9 <= eps <= 1e9 for FP32 arithmetic.
+// Evaluated in terms of the second differences t_r and the first
+// differences cb = c - b, dc = d - c, with which
+//   q0 - c = t0/3 + cb/2,  q1 - c = (cb + 2 dc)/6,  q2 - c = dc/2 - t2/6,
+//   (a-4b+3c)/2 = t0/2 + cb,  (b-d)/2 = -(cb + dc)/2,  (3c-4d+e)/2 = t2/2 - dc,
+// and the weights over the common denominator (eps+beta0)^2 (eps+beta1)^2
+// (eps+beta2)^2 (one reciprocal per face).  On a sliding window the t_r,
+// eps + 13/12 t_r^2 and the first differences are common subexpressions of
+// neighbouring faces.  FP32 range: (eps + beta)^4 must stay a normal number,
+// hence the library accepts 1e-9 <= eps <= 1e9 for FP32 arithmetic.
 // Every multiply-add is an explicit fma (the library is compiled without
-// automatic contraction), so an interface is the same function of its five
-// inputs wherever it is evaluated.
+// automatic contraction), so a face is the same function of its five inputs
+// wherever it is evaluated.
 template <typename CT>
 __device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
 {
-    const CT k13 = CT(13.0 / 12.0), q = CT(0.25);
-    const CT t0 = fmaT(CT(-2), b, a + c), u0 = fmaT(CT(2), c - b, t0);
-    const CT t1 = fmaT(CT(-2), c, b + d), u1 = b - d;
-    const CT t2 = fmaT(CT(-2), d, c + e), u2 = fmaT(CT(2), c - d, t2);
-    const CT s0 = fmaT(q * u0, u0, fmaT(k13 * t0, t0, eps));
-    const CT s1 = fmaT(q * u1, u1, fmaT(k13 * t1, t1, eps));
-    const CT s2 = fmaT(q * u2, u2, fmaT(k13 * t2, t2, eps));
+    const CT k13 = CT(13.0 / 12.0), h = CT(0.5);
+    const CT t0 = fmaT(CT(-2), b, a + c);
+    const CT t1 = fmaT(CT(-2), c, b + d);
+    const CT t2 = fmaT(CT(-2), d, c + e);
+    const CT cb = c - b, dc = d - c;
+    const CT T0 = fmaT(k13 * t0, t0, eps), T1 = fmaT(k13 * t1, t1, eps), T2 = fmaT(k13 * t2, t2, eps);
+    const CT v0 = fmaT(h, t0, cb), v1 = h * (cb + dc), v2 = fmaT(h, t2, -dc);
+    const CT s0 = fmaT(v0, v0, T0), s1 = fmaT(v1, v1, T1), s2 = fmaT(v2, v2, T2);
     const CT S0 = s0 * s0, S1 = s1 * s1, S2 = s2 * s2;
     const CT A0 = S1 * S2, A1 = S0 * S2, A2 = S0 * S1;
-    // (d_r / 6) * candidate polynomials
-    const CT Q0 = fmaT(CT(11.0 / 60.0), c, fmaT(CT(-7.0 / 60.0), b, CT(1.0 / 30.0) * a));
-    const CT Q1 = fmaT(CT(0.5), c, fmaT(CT(0.2), d, CT(-0.1) * b));
-    const CT Q2 = fmaT(CT(0.25), d, fmaT(CT(0.1), c, CT(-0.05) * e));
-    const CT num = fmaT(A0, Q0, fmaT(A1, Q1, A2 * Q2));
+    // d_r (q_r - c)
+    const CT R0 = fmaT(CT(1.0 / 30.0), t0, CT(0.05) * cb);
+    const CT R1 = fmaT(CT(0.2), dc, CT(0.1) * cb);
+    const CT R2 = fmaT(CT(-0.05), t2, CT(0.15) * dc);
+    const CT num = fmaT(A0, R0, fmaT(A1, R1, A2 * R2));
     const CT den = fmaT(CT(0.1), A0, fmaT(CT(0.6), A1, CT(0.3) * A2));
-    return num * fast_rcp(den);
-}
-
-// Face between LDS cells i and i + s (s = 1 along x, kLX along y); the
-// upwind side follows the sign of the velocity component.
-template <typename CT>
-__device__ __forceinline__ CT face_at(const CT *L, int i, int s, bool positive, CT eps)
-{
-    if (positive) return weno5(L[i - 2 * s], L[i - s], L[i], L[i + s], L[i + 2 * s], eps);
-    return weno5(L[i + 3 * s], L[i + 2 * s], L[i + s], L[i], L[i - s], eps);
+    return fmaT(num, fast_rcp(den), c);
 }
 
 __device__ __forceinline__ int wrap(int v, int n)
@@ -118,6 +116,10 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
     using CT = typename Arith<T>::type;
     __shared__ CT tile[2][kTileElems];
     __shared__ CT xface[kTY * kXFaceStride];
+    // FP32 storage: tiles and the Runge-Kutta base values are copied from
+    // global memory straight into LDS (global_load_lds), without registers
+    constexpr bool kDma = std::is_same<T, float>::value;
+    __shared__ CT gnl[kDma && WITH_GN ? kTY * kTX : 1];
 
     const int tid = threadIdx.x;
     const int lx = tid & 63, wy = tid >> 6;
@@ -164,33 +166,53 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
         for (int i = 0; i < kLoadsPerThread; ++i)
             if (toff[i] != -3) tile[buf][tid + i * kFdThreads] = reg[i];
     };
+    // asynchronous copy of tile k into tile[buf]; complete after a wait on
+    // the vector-memory counter
+    auto fetch_lds = [&](int k, int buf) {
+        const T *sk = src + k * P;
+        const int wave_base = tid & ~63;
+#pragma unroll
+        for (int i = 0; i < kLoadsPerThread; ++i) {
+            const int o = toff[i];
+            if (o >= 0) {
+                __builtin_amdgcn_global_load_lds(sk + o, &tile[buf][i * kFdThreads + wave_base], 4, 0, 0);
+            } else if (FIXED && o == -1) {
+                tile[buf][tid + i * kFdThreads] = p.ghost_l[k];
+            } else if (FIXED && o == -2) {
+                tile[buf][tid + i * kFdThreads] = p.ghost_r[k];
+            }
+        }
+    };
 
-    // --- moments of the thread's nodes ---
+    // --- the thread's nodes: column gx, rows gy0 .. gy0 + 7 ---
     const int gx = x0 + lx;
+    const int gy0 = y0 + wy * kRows;
     const bool colok = gx < Nx;
-    int noff[kRows];
-    bool active[kRows];
-    CT drho[kRows], rho[kRows], pxn[kRows][N + 1], pyn[kRows][N + 1];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const int gy = y0 + wy * kRows + r;
-        active[r] = colok && gy < Ny;
-        noff[r] = (gy < Ny ? gy : Ny - 1) * p.pitch + p.xoff + (colok ? gx : Nx - 1);
-    }
+    const int noff0 = p.xoff + (colok ? gx : Nx - 1);
+    auto node_off = [&](int r) {
+        const int gy = gy0 + r;
+        return (gy < Ny ? gy : Ny - 1) * p.pitch + noff0;
+    };
+    auto active = [&](int r) { return colok && gy0 + r < Ny; };
+
     CT pre[kLoadsPerThread];
-    fetch(0, pre);
+    if constexpr (kDma)
+        fetch_lds(0, 0);
+    else
+        fetch(0, pre);
+    CT drho[kRows], uxv[kRows], uyv[kRows];
     {
-        CT dr[kRows], jx[kRows], jy[kRows];
+        CT jx[kRows], jy[kRows];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) dr[r] = jx[r] = jy[r] = CT(0);
-#pragma unroll 4
+        for (int r = 0; r < kRows; ++r) drho[r] = jx[r] = jy[r] = CT(0);
+#pragma unroll 2
         for (int k = 0; k < p.K; ++k) {
             const CT vxk = p.vx[k], vyk = p.vy[k];
             const T *sk = src + k * P;
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
-                const CT g = ld(sk + noff[r]);
-                dr[r] += g;
+                const CT g = ld(sk + node_off(r));
+                drho[r] += g;
                 jx[r] = fmaT(g, vxk, jx[r]);
                 jy[r] = fmaT(g, vyk, jy[r]);
             }
@@ -203,79 +225,110 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
         }
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            drho[r] = dr[r];
-            rho[r] = p.rho0 + dr[r];
-            const CT inv = CT(1) / rho[r];
-            const CT ux = jx[r] * inv, uy = jy[r] * inv;
-            pxn[r][0] = pyn[r][0] = CT(1);
-#pragma unroll
-            for (int n = 1; n <= N; ++n) {
-                pxn[r][n] = pxn[r][n - 1] * ux;
-                pyn[r][n] = pyn[r][n - 1] * uy;
-            }
-            if (DIAG && active[r]) {
-                const int gy = y0 + wy * kRows + r;
-                acc.v[0] += (double)dr[r];
+            const CT rho = p.rho0 + drho[r];
+            const CT inv = CT(1) / rho;
+            uxv[r] = jx[r] * inv;
+            uyv[r] = jy[r] * inv;
+            if (DIAG && active(r)) {
+                const int gy = gy0 + r;
+                acc.v[0] += (double)drho[r];
                 acc.v[1] += (double)jx[r];
                 acc.v[2] += (double)jy[r];
-                acc.v[3] += (double)(CT(0.5) * rho[r] * fmaT(ux, ux, uy * uy));
-                if (d.ax) acc.v[4] += (double)fmaT(ux, pax * d.ay[gy], uy * (pbx * d.by[gy]));
+                acc.v[3] += (double)(CT(0.5) * rho * fmaT(uxv[r], uxv[r], uyv[r] * uyv[r]));
+                if (d.ax) acc.v[4] += (double)fmaT(uxv[r], pax * d.ay[gy], uyv[r] * (pbx * d.by[gy]));
             }
         }
         if (DIAG) block_diag_store(acc, d.partial, blockIdx.y * gridDim.x + blockIdx.x);
     }
 
     const CT eps = p.eps, dt = p.dt, inv_tau = p.inv_tau;
-    stash(0, pre);
-    if (p.K > 1) fetch(1, pre);
+    if constexpr (kDma) {
+        __builtin_amdgcn_s_waitcnt(0);
+    } else {
+        stash(0, pre);
+        if (p.K > 1) fetch(1, pre);
+    }
     __syncthreads();
 
     const int c0 = (wy * kRows + kHalo) * kLX + lx + kHalo;  // LDS cell of the thread's first node
+    const int xr = tid / (kTX / kSeg), xs = tid % (kTX / kSeg);   // x-face row and segment
+    const int xw = (xr + kHalo) * kLX + xs * kSeg + kHalo;        // LDS cell of the segment's first column
 
     for (int k = 0; k < p.K; ++k) {
         const int buf = k & 1;
         const CT *L = tile[buf];
         const CT vxk = p.vx[k], vyk = p.vy[k];
-        const bool xpos = vxk > CT(0), ypos = vyk > CT(0);
 
         CT gnv[kRows];
-        if (WITH_GN) {
+        if constexpr (kDma) {
+            if (WITH_GN) {
+                const T *gk = gn + k * P;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r)
+                    __builtin_amdgcn_global_load_lds(gk + node_off(r), &gnl[(wy * kRows + r) * kTX], 4, 0, 0);
+            }
+            if (k + 1 < p.K) fetch_lds(k + 1, buf ^ 1);
+        } else if (WITH_GN) {
             const T *gk = gn + k * P;
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) gnv[r] = ld(gk + noff[r]);
+            for (int r = 0; r < kRows; ++r) gnv[r] = ld(gk + node_off(r));
         }
 
-        // a. x-faces: right face of each node; left face of column 0 by 16 lanes
-        CT fr[kRows];
+        // a. x-faces: faces xs*8 + 1 .. xs*8 + 8 of row xr (face i lies between
+        //    tile columns i-1 and i), marching; column-0 faces by 32 lanes
         if (vxk != CT(0)) {
+            CT w[kSeg + 4];
+            CT *fx = &xface[xr * kXFaceStride + xs * kSeg + 1];
+            if (vxk > CT(0)) {
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) {
-                fr[r] = face_at(L, c0 + r * kLX, 1, xpos, eps);
-                xface[(wy * kRows + r) * kXFaceStride + lx + 1] = fr[r];
+                for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 2 + i];
+#pragma unroll
+                for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
+                if (tid < kTY) {
+                    const int b = (tid + kHalo) * kLX + kHalo - 1;  // upwind cell of the column-0 face
+                    xface[tid * kXFaceStride] = weno5(L[b - 2], L[b - 1], L[b], L[b + 1], L[b + 2], eps);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 1 + i];
+#pragma unroll
+                for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
+                if (tid < kTY) {
+                    const int b = (tid + kHalo) * kLX + kHalo;  // upwind cell of the column-0 face
+                    xface[tid * kXFaceStride] = weno5(L[b + 2], L[b + 1], L[b], L[b - 1], L[b - 2], eps);
+                }
             }
-            if (wy == 0 && lx < kTY)
-                xface[lx * kXFaceStride] = face_at(L, (lx + kHalo) * kLX + kHalo - 1, 1, xpos, eps);
         }
 
-        // b. y-faces: march up the column, 5 faces for the 4 nodes
+        // b. y-faces: march up the column, 9 faces for the 8 nodes
         CT dfy[kRows];
         if (vyk != CT(0)) {
-            CT w[9];
-            const int wb = c0 + (ypos ? -3 : -2) * kLX;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) w[i] = L[wb + i * kLX];
+            CT w[kRows + 5];
             CT prev = CT(0);
+            if (vyk > CT(0)) {
 #pragma unroll
-            for (int m = 0; m <= kRows; ++m) {
-                const CT G = ypos ? weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps)
-                                  : weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
-                if (m > 0) dfy[m - 1] = G - prev;
-                prev = G;
+                for (int i = 0; i < kRows + 5; ++i) w[i] = L[c0 + (i - 3) * kLX];
+#pragma unroll
+                for (int m = 0; m <= kRows; ++m) {
+                    const CT G = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
+                    if (m > 0) dfy[m - 1] = G - prev;
+                    prev = G;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kRows + 5; ++i) w[i] = L[c0 + (i - 2) * kLX];
+#pragma unroll
+                for (int m = 0; m <= kRows; ++m) {
+                    const CT G = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
+                    if (m > 0) dfy[m - 1] = G - prev;
+                    prev = G;
+                }
             }
         } else {
 #pragma unroll
             for (int r = 0; r < kRows; ++r) dfy[r] = CT(0);
         }
+        if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
         __syncthreads();
 
         // c. node updates
@@ -290,33 +343,51 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
         }
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
+            const int tr = wy * kRows + r;  // tile row
             const CT g = L[c0 + r * kLX];
-            const CT dfx = (vxk != CT(0)) ? fr[r] - xface[(wy * kRows + r) * kXFaceStride + lx] : CT(0);
+            const CT dfx = (vxk != CT(0)) ? xface[tr * kXFaceStride + lx + 1] - xface[tr * kXFaceStride + lx] : CT(0);
 
             // order-N equilibrium, shifted:  w_k [drho + rho P'(u)],
             // P' = sum_{1 <= n+m <= N} a_n b_m with a_n = He_n(xi_i) ux^n / n!,
             // b_m = He_m(xi_j) uy^m / m!, summed as C'_N + sum_n a_n (1 + C'_{N-n}),
             // C'_r = b_1 + ... + b_r (no O(1) term, so no cancellation).
+            CT px[N + 1], py[N + 1];
+            px[1] = uxv[r];
+            py[1] = uyv[r];
+#pragma unroll
+            for (int n = 2; n <= N; ++n) {
+                px[n] = px[n - 1] * uxv[r];
+                py[n] = py[n - 1] * uyv[r];
+            }
             CT cpre[N + 1];
             cpre[0] = CT(0);
 #pragma unroll
-            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(hy[m], pyn[r][m], cpre[m - 1]);
+            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(hy[m], py[m], cpre[m - 1]);
             CT pp = cpre[N];
 #pragma unroll
-            for (int n = 1; n <= N; ++n) pp = fmaT(hx[n] * pxn[r][n], CT(1) + cpre[N - n], pp);
-            const CT geq = wk * fmaT(rho[r], pp, drho[r]);
+            for (int n = 1; n <= N; ++n) pp = fmaT(hx[n] * px[n], CT(1) + cpre[N - n], pp);
+            const CT geq = wk * fmaT(p.rho0 + drho[r], pp, drho[r]);
 
             const CT adv = fmaT(vxs, dfx, vys * dfy[r]);
             const CT Lk = -fmaT(g - geq, inv_tau, adv);
             CT res = fmaT(dt, Lk, g);
-            if (WITH_GN) res = fmaT(cb, res - gnv[r], gnv[r]);
-            if (active[r]) store_from(out + k * P + noff[r], res);
+            if (WITH_GN) {
+                CT b;
+                if constexpr (kDma)
+                    b = gnl[tr * kTX + lx];
+                else
+                    b = gnv[r];
+                res = fmaT(cb, res - b, b);
+            }
+            if (active(r)) store_from(out + k * P + node_off(r), res);
         }
 
         // d. next tile into the other LDS buffer, prefetch the one after
-        if (k + 1 < p.K) {
-            stash(buf ^ 1, pre);
-            if (k + 2 < p.K) fetch(k + 2, pre);
+        if constexpr (!kDma) {
+            if (k + 1 < p.K) {
+                stash(buf ^ 1, pre);
+                if (k + 2 < p.K) fetch(k + 2, pre);
+            }
         }
         __syncthreads();
     }
