@@ -174,6 +174,77 @@ int lb_synchronize(lb_sim *sim);
 /* Device bytes held by the handle. */
 size_t lb_device_bytes(const lb_sim *sim);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many independent simulations.
+ *
+ * A server owns one HIP stream and a worker thread.  Submitted requests wait
+ * in a queue; the worker admits them while the device-memory budget and the
+ * slot count allow (footprint = state buffers + diagnostics of the
+ * simulation), initialises them, and advances every admitted simulation by
+ * one step per batched launch (one launch for all collision-streaming
+ * simulations, three stage launches per equilibrium order for the
+ * finite-difference ones).  Requests that arrive while others run are
+ * admitted between chunks of batched steps as memory frees up; a finished
+ * simulation is drained (final diagnostics), its memory released and its
+ * result queued for lb_server_poll.  Each simulation computes the same
+ * values as a single lb_sim run of the same request (same per-row / per-tile
+ * device code), whatever else shares the batch.
+ * Supported requests: periodic, FP32 storage, any model.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_server lb_server;
+
+typedef struct lb_request {
+    int model;                /* lb_model (FP32 storage) */
+    int Nx, Ny;
+    double tau, dt, ds;       /* as for lb_create */
+    int N;                    /* equilibrium order */
+    const double *rho, *ux, *uy;         /* initial fields [Ny][Nx]; read at admission, so they
+                                            must stay valid until the request's result is polled */
+    const double *ax, *ay, *bx, *by;     /* separable probe (as lb_set_probe), all NULL for none */
+    int nsteps;               /* steps to run, >= 1 */
+    int sample_every;         /* diagnostics every this many steps, >= 1 */
+    uint64_t tag;             /* returned in the result */
+} lb_request;
+
+typedef struct lb_result {
+    uint64_t id, tag;
+    int status;               /* LB_OK or the error that ended the request */
+    int nsamples;
+    double *samples;          /* nsamples rows {t, M, Px, Py, E, A}: the states at
+                                 t = 0, every, 2 every, ... < nsteps and the final state
+                                 t = nsteps; owned by the server until lb_server_release */
+    double t_submit, t_admit, t_finish;  /* seconds on the server clock */
+} lb_result;
+
+/* hbm_budget_bytes: device memory the admitted simulations may hold;
+ * max_slots: simulations admitted at once (1..4096); chunk_steps: batched
+ * steps between admission / drain points (>= 1).  NULL on error. */
+lb_server *lb_server_create(size_t hbm_budget_bytes, int max_slots, int chunk_steps);
+
+/* Queue a request (non-blocking).  LB_EINVAL for a request that lb_create
+ * would reject or that is not supported in a batch; LB_EBUSY when the
+ * request alone exceeds the budget.  *id receives the request id. */
+int lb_server_submit(lb_server *srv, const lb_request *req, uint64_t *id);
+
+/* Move up to max finished results into out, waiting up to timeout_us for
+ * the first one.  Returns the number of results (>= 0). */
+int lb_server_poll(lb_server *srv, lb_result *out, int max, int timeout_us);
+
+/* Free the samples of a polled result. */
+void lb_server_release(lb_server *srv, lb_result *res);
+
+/* Seconds since the server was created (the clock of the time stamps). */
+double lb_server_clock(const lb_server *srv);
+
+/* Counters: out[0] submitted, out[1] completed, out[2] queued, out[3]
+ * running, out[4] device bytes held, out[5] batched steps launched,
+ * out[6] seconds the worker spent with simulations on the device. */
+int lb_server_stats(const lb_server *srv, double out[7]);
+
+/* Stop the worker (running and queued requests are abandoned) and release
+ * every resource.  NULL is ignored. */
+void lb_server_destroy(lb_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

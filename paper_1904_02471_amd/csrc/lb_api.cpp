@@ -13,6 +13,7 @@
 #include "lb.h"
 #include "lb_internal.h"
 #include "lb_model.h"
+#include "lb_sim_impl.h"
 
 using namespace lbm;
 
@@ -26,45 +27,10 @@ int fail(int code)
     return code;
 }
 
-enum Prec { P32 = 0, P16 = 1, P64 = 2 };
-
 }  // namespace
 
-struct lb_sim {
-    int model = 0;
-    Prec prec = P32;
-    bool cs = true;
-    int Nx = 0, Ny = 0, K = 0, Q = 0, N = 0;
-    double tau = 0, dt = 0, ds = 0;
-    ModelInfo mi{};
-    double rho0 = 1.0;
-    bool fixed = false;
-    double rho_l = 1.0, rho_r = 1.0;
-    double eps = 1e-6;
-    bool ready = false;
-    long long steps = 0;
-    int cur = 0;  // CS: buffer holding the current state
-    int pitch = 0, xoff = 0;
-    long long plane = 0;
-    size_t esize = 4;
-    int nbuf = 0;
-    void *buf[3] = {nullptr, nullptr, nullptr};
-    size_t buf_bytes = 0;
-    hipStream_t stream = nullptr, own_stream = nullptr;
-    double *d_partial = nullptr;  // per-block diagnostics partials
-    int partial_blocks = 0;
-    double *d_out = nullptr;      // kDiag doubles
-    bool probe = false;
-    double probe_den = 0.0;
-    double *d_probe64 = nullptr;  // ax | ay | bx | by
-    float *d_probe32 = nullptr;
-    double *d_series = nullptr;   // [series_cap][kDiag] raw sums
-    int series_cap = 0;
-    std::vector<long long> series_t;  // step index of each pending sample
-    std::vector<char> series_fused;   // sums in the step kernel's velocity unit
-};
 
-namespace {
+namespace lbm {
 
 size_t elem_size(Prec p) { return p == P16 ? 2 : (p == P64 ? 8 : 4); }
 
@@ -218,6 +184,34 @@ hipError_t reduce_into(lb_sim *s, double *d_dst)
     return e;
 }
 
+int set_last_error(int code) { return fail(code); }
+
+int validate_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N)
+{
+    const int model = model_flags & 0xff;
+    const int precbits = model_flags & LB_PRECISION_MASK;
+    if ((model_flags & ~(0xff | LB_PRECISION_MASK)) != 0 || precbits == (3 << 8)) return LB_EINVAL;
+    ModelInfo mi{};
+    if (!(tau > 0) || !(dt > 0) || !(ds > 0) || !std::isfinite(tau) || !std::isfinite(dt) || !std::isfinite(ds) ||
+        Nx < 1 || Ny < 1 || (long long)Nx * Ny > (1LL << 30) || !model_info(model, ds, dt, &mi))
+        return LB_EINVAL;
+    if (model == LB_CS_D2Q9) {
+        // positive viscosity nu = c_s^2 (tau - dt/2) (Section 2)
+        if (N != 2 || !(tau > 0.5 * dt)) return LB_EINVAL;
+        return LB_OK;
+    }
+    if (N < 1 || N > mi.Q - 1) return LB_EINVAL;
+    // CFL = max |v_k,alpha| dt / ds <= 1 and dt < tau (Section 4.1); dt == tau
+    // is accepted, as in the shear-wave runs of Section 4.2
+    const double vmax = mi.xi[mi.Q - 1];
+    if (vmax * dt / ds > 1.0 + 1e-12) return LB_ECFL;
+    if (dt > tau * (1.0 + 1e-12)) return LB_ESTIFF;
+    return LB_OK;
+}
+
+template Params<float> make_params<float>(const lb_sim *);
+template Params<double> make_params<double>(const lb_sim *);
+
 bool all_finite(const double *v, size_t n)
 {
     for (size_t i = 0; i < n; ++i)
@@ -225,7 +219,7 @@ bool all_finite(const double *v, size_t n)
     return true;
 }
 
-}  // namespace
+}  // namespace lbm
 
 extern "C" {
 
@@ -262,42 +256,16 @@ int lb_model_info(int model, double ds, double dt, double *vx, double *vy, doubl
 
 lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N)
 {
+    const int vrc = lbm::validate_create(model_flags, Nx, Ny, tau, dt, ds, N);
+    if (vrc != LB_OK) {
+        fail(vrc);
+        return nullptr;
+    }
     const int model = model_flags & 0xff;
     const int precbits = model_flags & LB_PRECISION_MASK;
-    if ((model_flags & ~(0xff | LB_PRECISION_MASK)) != 0 || precbits == (3 << 8)) {
-        fail(LB_EINVAL);
-        return nullptr;
-    }
     ModelInfo mi{};
-    if (!(tau > 0) || !(dt > 0) || !(ds > 0) || !std::isfinite(tau) || !std::isfinite(dt) || !std::isfinite(ds) ||
-        Nx < 1 || Ny < 1 || (long long)Nx * Ny > (1LL << 30) || !model_info(model, ds, dt, &mi)) {
-        fail(LB_EINVAL);
-        return nullptr;
-    }
+    model_info(model, ds, dt, &mi);
     const bool cs = model == LB_CS_D2Q9;
-    if (cs) {
-        // positive viscosity nu = c_s^2 (tau - dt/2) (Section 2)
-        if (N != 2 || !(tau > 0.5 * dt)) {
-            fail(LB_EINVAL);
-            return nullptr;
-        }
-    } else {
-        if (N < 1 || N > mi.Q - 1) {
-            fail(LB_EINVAL);
-            return nullptr;
-        }
-        // CFL = max |v_k,alpha| dt / ds <= 1 and dt < tau (Section 4.1);
-        // dt == tau is accepted, as in the shear-wave runs of Section 4.2
-        const double vmax = mi.xi[mi.Q - 1];
-        if (vmax * dt / ds > 1.0 + 1e-12) {
-            fail(LB_ECFL);
-            return nullptr;
-        }
-        if (dt > tau * (1.0 + 1e-12)) {
-            fail(LB_ESTIFF);
-            return nullptr;
-        }
-    }
     lb_sim *s = new (std::nothrow) lb_sim();
     if (!s) {
         fail(LB_ENOMEM);

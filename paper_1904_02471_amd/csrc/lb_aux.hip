@@ -154,23 +154,9 @@ __global__ __launch_bounds__(kAuxThreads) void reduce_kernel(const T *src, bool 
     block_diag_store(acc, d.partial, blockIdx.x);
 }
 
-// One block: thread t sums partials t, t + 256, ... in order, then a fixed
-// pairwise tree over the 256 thread sums.
 __global__ __launch_bounds__(kAuxThreads) void diag_finalize_kernel(const double *partial, int nblocks, double *out)
 {
-    __shared__ double s[kDiag][kAuxThreads];
-    const int t = threadIdx.x;
-    double a[kDiag] = {0, 0, 0, 0, 0};
-    for (int b = t; b < nblocks; b += kAuxThreads)
-        for (int i = 0; i < kDiag; ++i) a[i] += partial[(long long)b * kDiag + i];
-    for (int i = 0; i < kDiag; ++i) s[i][t] = a[i];
-    __syncthreads();
-    for (int h = kAuxThreads / 2; h > 0; h >>= 1) {
-        if (t < h)
-            for (int i = 0; i < kDiag; ++i) s[i][t] += s[i][t + h];
-        __syncthreads();
-    }
-    if (t < kDiag) out[t] = s[t][0];
+    diag_finalize_block(partial, nblocks, out);
 }
 
 unsigned grid_for(long long n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }

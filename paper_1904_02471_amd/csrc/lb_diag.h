@@ -39,4 +39,25 @@ __device__ __forceinline__ void block_diag_store(DiagAcc &acc, double *partial, 
     }
 }
 
+// Sum nblocks partials into out[kDiag] in a fixed order, by one workgroup
+// of 256 threads: thread t sums partials t, t + 256, ... in order, then a
+// pairwise tree over the 256 thread sums.
+__device__ __forceinline__ void diag_finalize_block(const double *partial, int nblocks, double *out)
+{
+    constexpr int kT = 256;
+    __shared__ double s[kDiag][kT];
+    const int t = threadIdx.x;
+    double a[kDiag] = {0, 0, 0, 0, 0};
+    for (int b = t; b < nblocks; b += kT)
+        for (int i = 0; i < kDiag; ++i) a[i] += partial[(long long)b * kDiag + i];
+    for (int i = 0; i < kDiag; ++i) s[i][t] = a[i];
+    __syncthreads();
+    for (int h = kT / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int i = 0; i < kDiag; ++i) s[i][t] += s[i][t + h];
+        __syncthreads();
+    }
+    if (t < kDiag) out[t] = s[t][0];
+}
+
 }  // namespace lbm

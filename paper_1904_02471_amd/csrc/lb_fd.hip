@@ -1,111 +1,10 @@
-// lb_fd.hip -- finite-difference Gauss-Hermite step for gfx950: one launch
-// per stage of the third-order TVD Runge-Kutta scheme (Section 2),
-//
-//   L(g)_k = -[v_kx (F_{i+1/2} - F_{i-1/2}) + v_ky (G_{j+1/2} - G_{j-1/2})] / ds
-//            - (g_k - g_eq_k(g)) / tau
-//   stage 1: A  = g + dt L(g)
-//   stage 2: B  = g + 1/4 (A + dt L(A) - g)           (= 3/4 g + 1/4 (A + dt L(A)))
-//   stage 3: g' = g + 2/3 (B + dt L(B) - g)           (= 1/3 g + 2/3 (B + dt L(B)))
-//
-// with F, G the WENO-5 reconstructions on the upwind side of each interface
-// and g_eq the Hermite equilibrium of order N (Section 1).  The combinations
-// are written as g + c (x - g) so that the two weights sum to one exactly in
-// floating point (1/3 and 2/3 do not): no spurious growth of the state.
-//
-// The stage is bound by vector-ALU issue (the WENO-5 face is the bulk of the
-// work), so the mapping evaluates every face once and marches along rows and
-// columns so that neighbouring faces share their differences and smoothness
-// terms:
-//
-//   A workgroup of 256 threads owns a 64 x 32 tile; thread (lx, wy) owns
-//   column lx and the 8 rows 8 wy .. 8 wy + 7.
-//   1. moments: the thread gathers the K values of its 8 nodes and keeps
-//      drho, u_x, u_y per node.
-//   2. loop over the populations k; the tile of population k with a 3-node
-//      halo is staged in LDS (double-buffered; the next tile is prefetched
-//      into registers while the current one is used):
-//      a. x-faces: thread (row tid / 8, segment tid % 8) marches along its
-//         row over 8 faces from a 12-value register window; 32 lanes add the
-//         left face of column 0 of the 32 rows; faces go to LDS;
-//      b. y-faces: thread (lx, wy) marches up its column, 9 faces for its 8
-//         nodes, from a 13-value register window, in registers;
-//      c. node update: flux differences, order-N equilibrium of population
-//         k, Runge-Kutta combination, store.
-//   The sign of v_kx / v_ky is uniform over the launch, so the upwind side
-//   is a scalar branch and every LDS access has a constant offset.
-#include <type_traits>
-
-#include "lb_diag.h"
-#include "lb_internal.h"
+// lb_fd.hip -- finite-difference Gauss-Hermite stage kernels for gfx950, one
+// simulation per launch (device code in lb_fd_impl.h).
+#include "lb_fd_impl.h"
 
 namespace lbm {
 
 namespace {
-
-constexpr int kTX = 64, kTY = 32, kRows = 8;
-constexpr int kFdThreads = 256;
-constexpr int kHalo = 3;
-constexpr int kLX = kTX + 2 * kHalo;  // 70
-constexpr int kLY = kTY + 2 * kHalo;  // 38
-constexpr int kTileElems = kLX * kLY;
-constexpr int kLoadsPerThread = (kTileElems + kFdThreads - 1) / kFdThreads;
-constexpr int kXFaceStride = kTX + 1;  // x-faces per tile row
-constexpr int kSeg = 8;                // x-faces per marching segment
-static_assert(kTY * (kTX / kSeg) == kFdThreads, "one x-face segment per thread");
-static_assert(kTY <= 64, "the column-0 faces are computed by one wave");
-
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// WENO-5 (Jiang-Shu) interface value downstream of cell c from the values
-// a, b, c, d, e ordered along the upwind direction:
-//   candidates q0 = (2a - 7b + 11c)/6, q1 = (-b + 5c + 2d)/6, q2 = (2c + 5d - e)/6
-//   smoothness beta0 = 13/12 (a-2b+c)^2 + 1/4 (a-4b+3c)^2,
-//              beta1 = 13/12 (b-2c+d)^2 + 1/4 (b-d)^2,
-//              beta2 = 13/12 (c-2d+e)^2 + 1/4 (3c-4d+e)^2
-//   weights    alpha_r = d_r / (eps + beta_r)^2, d = (0.1, 0.6, 0.3)
-//   value      sum alpha_r q_r / sum alpha_r.
-// Evaluated in terms of the second differences t_r and the first
-// differences cb = c - b, dc = d - c, with which
-//   q0 - c = t0/3 + cb/2,  q1 - c = (cb + 2 dc)/6,  q2 - c = dc/2 - t2/6,
-//   (a-4b+3c)/2 = t0/2 + cb,  (b-d)/2 = -(cb + dc)/2,  (3c-4d+e)/2 = t2/2 - dc,
-// and the weights over the common denominator (eps+beta0)^2 (eps+beta1)^2
-// (eps+beta2)^2 (one reciprocal per face).  On a sliding window the t_r,
-// eps + 13/12 t_r^2 and the first differences are common subexpressions of
-// neighbouring faces.  FP32 range: (eps + beta)^4 must stay a normal number,
-// hence the library accepts 1e-9 <= eps <= 1e9 for FP32 arithmetic.
-// Every multiply-add is an explicit fma (the library is compiled without
-// automatic contraction), so a face is the same function of its five inputs
-// wherever it is evaluated.
-template <typename CT>
-__device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
-{
-    const CT k13 = CT(13.0 / 12.0), h = CT(0.5);
-    const CT t0 = fmaT(CT(-2), b, a + c);
-    const CT t1 = fmaT(CT(-2), c, b + d);
-    const CT t2 = fmaT(CT(-2), d, c + e);
-    const CT cb = c - b, dc = d - c;
-    const CT T0 = fmaT(k13 * t0, t0, eps), T1 = fmaT(k13 * t1, t1, eps), T2 = fmaT(k13 * t2, t2, eps);
-    const CT v0 = fmaT(h, t0, cb), v1 = h * (cb + dc), v2 = fmaT(h, t2, -dc);
-    const CT s0 = fmaT(v0, v0, T0), s1 = fmaT(v1, v1, T1), s2 = fmaT(v2, v2, T2);
-    const CT S0 = s0 * s0, S1 = s1 * s1, S2 = s2 * s2;
-    const CT A0 = S1 * S2, A1 = S0 * S2, A2 = S0 * S1;
-    // d_r (q_r - c)
-    const CT R0 = fmaT(CT(1.0 / 30.0), t0, CT(0.05) * cb);
-    const CT R1 = fmaT(CT(0.2), dc, CT(0.1) * cb);
-    const CT R2 = fmaT(CT(-0.05), t2, CT(0.15) * dc);
-    const CT num = fmaT(A0, R0, fmaT(A1, R1, A2 * R2));
-    const CT den = fmaT(CT(0.1), A0, fmaT(CT(0.6), A1, CT(0.3) * A2));
-    return fmaT(num, fast_rcp(den), c);
-}
-
-__device__ __forceinline__ int wrap(int v, int n)
-{
-    int r = v % n;
-    return r < 0 ? r + n : r;
-}
 
 template <typename T, int N, bool FIXED, bool DIAG, bool WITH_GN>
 __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
@@ -113,284 +12,8 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
                                                               const Params<typename Arith<T>::type> p,
                                                               const DiagArgs<typename Arith<T>::type> d)
 {
-    using CT = typename Arith<T>::type;
-    __shared__ CT tile[2][kTileElems];
-    __shared__ CT xface[kTY * kXFaceStride];
-    // FP32 storage: tiles and the Runge-Kutta base values are copied from
-    // global memory straight into LDS (global_load_lds), without registers
-    constexpr bool kDma = std::is_same<T, float>::value;
-    __shared__ CT gnl[kDma && WITH_GN ? kTY * kTX : 1];
-
-    const int tid = threadIdx.x;
-    const int lx = tid & 63, wy = tid >> 6;
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
-    const int Nx = p.Nx, Ny = p.Ny;
-    const long long P = p.plane;
-
-    // --- offsets of the tile elements this thread stages (fixed over k) ---
-    // >= 0: element offset inside a plane; -1 / -2: left / right end state;
-    // -3: no element
-    int toff[kLoadsPerThread];
-#pragma unroll
-    for (int i = 0; i < kLoadsPerThread; ++i) {
-        const int e = tid + i * kFdThreads;
-        if (e < kTileElems) {
-            const int r = e / kLX, c = e - r * kLX;
-            const int gy = wrap(y0 - kHalo + r, Ny);
-            const int gxr = x0 - kHalo + c;
-            if (FIXED && gxr < 0)
-                toff[i] = -1;
-            else if (FIXED && gxr >= Nx)
-                toff[i] = -2;
-            else
-                toff[i] = gy * p.pitch + p.xoff + wrap(gxr, Nx);
-        } else {
-            toff[i] = -3;
-        }
-    }
-    auto fetch = [&](int k, CT *reg) {
-        const T *sk = src + k * P;
-#pragma unroll
-        for (int i = 0; i < kLoadsPerThread; ++i) {
-            const int o = toff[i];
-            if (o >= 0)
-                reg[i] = ld(sk + o);
-            else if (FIXED && o == -1)
-                reg[i] = p.ghost_l[k];
-            else if (FIXED && o == -2)
-                reg[i] = p.ghost_r[k];
-        }
-    };
-    auto stash = [&](int buf, const CT *reg) {
-#pragma unroll
-        for (int i = 0; i < kLoadsPerThread; ++i)
-            if (toff[i] != -3) tile[buf][tid + i * kFdThreads] = reg[i];
-    };
-    // asynchronous copy of tile k into tile[buf]; complete after a wait on
-    // the vector-memory counter
-    auto fetch_lds = [&](int k, int buf) {
-        const T *sk = src + k * P;
-        const int wave_base = tid & ~63;
-#pragma unroll
-        for (int i = 0; i < kLoadsPerThread; ++i) {
-            const int o = toff[i];
-            if (o >= 0) {
-                __builtin_amdgcn_global_load_lds(sk + o, &tile[buf][i * kFdThreads + wave_base], 4, 0, 0);
-            } else if (FIXED && o == -1) {
-                tile[buf][tid + i * kFdThreads] = p.ghost_l[k];
-            } else if (FIXED && o == -2) {
-                tile[buf][tid + i * kFdThreads] = p.ghost_r[k];
-            }
-        }
-    };
-
-    // --- the thread's nodes: column gx, rows gy0 .. gy0 + 7 ---
-    const int gx = x0 + lx;
-    const int gy0 = y0 + wy * kRows;
-    const bool colok = gx < Nx;
-    const int noff0 = p.xoff + (colok ? gx : Nx - 1);
-    auto node_off = [&](int r) {
-        const int gy = gy0 + r;
-        return (gy < Ny ? gy : Ny - 1) * p.pitch + noff0;
-    };
-    auto active = [&](int r) { return colok && gy0 + r < Ny; };
-
-    CT pre[kLoadsPerThread];
-    if constexpr (kDma)
-        fetch_lds(0, 0);
-    else
-        fetch(0, pre);
-    CT drho[kRows], uxv[kRows], uyv[kRows];
-    {
-        CT jx[kRows], jy[kRows];
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) drho[r] = jx[r] = jy[r] = CT(0);
-#pragma unroll 2
-        for (int k = 0; k < p.K; ++k) {
-            const CT vxk = p.vx[k], vyk = p.vy[k];
-            const T *sk = src + k * P;
-#pragma unroll
-            for (int r = 0; r < kRows; ++r) {
-                const CT g = ld(sk + node_off(r));
-                drho[r] += g;
-                jx[r] = fmaT(g, vxk, jx[r]);
-                jy[r] = fmaT(g, vyk, jy[r]);
-            }
-        }
-        DiagAcc acc;
-        CT pax = CT(0), pbx = CT(0);
-        if (DIAG && d.ax) {
-            pax = d.ax[colok ? gx : 0];
-            pbx = d.bx[colok ? gx : 0];
-        }
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const CT rho = p.rho0 + drho[r];
-            const CT inv = CT(1) / rho;
-            uxv[r] = jx[r] * inv;
-            uyv[r] = jy[r] * inv;
-            if (DIAG && active(r)) {
-                const int gy = gy0 + r;
-                acc.v[0] += (double)drho[r];
-                acc.v[1] += (double)jx[r];
-                acc.v[2] += (double)jy[r];
-                acc.v[3] += (double)(CT(0.5) * rho * fmaT(uxv[r], uxv[r], uyv[r] * uyv[r]));
-                if (d.ax) acc.v[4] += (double)fmaT(uxv[r], pax * d.ay[gy], uyv[r] * (pbx * d.by[gy]));
-            }
-        }
-        if (DIAG) block_diag_store(acc, d.partial, blockIdx.y * gridDim.x + blockIdx.x);
-    }
-
-    const CT eps = p.eps, dt = p.dt, inv_tau = p.inv_tau;
-    if constexpr (kDma) {
-        __builtin_amdgcn_s_waitcnt(0);
-    } else {
-        stash(0, pre);
-        if (p.K > 1) fetch(1, pre);
-    }
-    __syncthreads();
-
-    const int c0 = (wy * kRows + kHalo) * kLX + lx + kHalo;  // LDS cell of the thread's first node
-    const int xr = tid / (kTX / kSeg), xs = tid % (kTX / kSeg);   // x-face row and segment
-    const int xw = (xr + kHalo) * kLX + xs * kSeg + kHalo;        // LDS cell of the segment's first column
-
-    for (int k = 0; k < p.K; ++k) {
-        const int buf = k & 1;
-        const CT *L = tile[buf];
-        const CT vxk = p.vx[k], vyk = p.vy[k];
-
-        CT gnv[kRows];
-        if constexpr (kDma) {
-            if (WITH_GN) {
-                const T *gk = gn + k * P;
-#pragma unroll
-                for (int r = 0; r < kRows; ++r)
-                    __builtin_amdgcn_global_load_lds(gk + node_off(r), &gnl[(wy * kRows + r) * kTX], 4, 0, 0);
-            }
-            if (k + 1 < p.K) fetch_lds(k + 1, buf ^ 1);
-        } else if (WITH_GN) {
-            const T *gk = gn + k * P;
-#pragma unroll
-            for (int r = 0; r < kRows; ++r) gnv[r] = ld(gk + node_off(r));
-        }
-
-        // a. x-faces: faces xs*8 + 1 .. xs*8 + 8 of row xr (face i lies between
-        //    tile columns i-1 and i), marching; column-0 faces by 32 lanes
-        if (vxk != CT(0)) {
-            CT w[kSeg + 4];
-            CT *fx = &xface[xr * kXFaceStride + xs * kSeg + 1];
-            if (vxk > CT(0)) {
-#pragma unroll
-                for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 2 + i];
-#pragma unroll
-                for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
-                if (tid < kTY) {
-                    const int b = (tid + kHalo) * kLX + kHalo - 1;  // upwind cell of the column-0 face
-                    xface[tid * kXFaceStride] = weno5(L[b - 2], L[b - 1], L[b], L[b + 1], L[b + 2], eps);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 1 + i];
-#pragma unroll
-                for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
-                if (tid < kTY) {
-                    const int b = (tid + kHalo) * kLX + kHalo;  // upwind cell of the column-0 face
-                    xface[tid * kXFaceStride] = weno5(L[b + 2], L[b + 1], L[b], L[b - 1], L[b - 2], eps);
-                }
-            }
-        }
-
-        // b. y-faces: march up the column, 9 faces for the 8 nodes
-        CT dfy[kRows];
-        if (vyk != CT(0)) {
-            CT w[kRows + 5];
-            CT prev = CT(0);
-            if (vyk > CT(0)) {
-#pragma unroll
-                for (int i = 0; i < kRows + 5; ++i) w[i] = L[c0 + (i - 3) * kLX];
-#pragma unroll
-                for (int m = 0; m <= kRows; ++m) {
-                    const CT G = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
-                    if (m > 0) dfy[m - 1] = G - prev;
-                    prev = G;
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < kRows + 5; ++i) w[i] = L[c0 + (i - 2) * kLX];
-#pragma unroll
-                for (int m = 0; m <= kRows; ++m) {
-                    const CT G = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
-                    if (m > 0) dfy[m - 1] = G - prev;
-                    prev = G;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < kRows; ++r) dfy[r] = CT(0);
-        }
-        if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
-        __syncthreads();
-
-        // c. node updates
-        const int qi = p.ki[k], qj = p.kj[k];
-        const CT wk = p.w[k];
-        const CT vxs = vxk * p.inv_ds, vys = vyk * p.inv_ds;
-        CT hx[N + 1], hy[N + 1];
-#pragma unroll
-        for (int n = 1; n <= N; ++n) {
-            hx[n] = p.hc[qi][n];
-            hy[n] = p.hc[qj][n];
-        }
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const int tr = wy * kRows + r;  // tile row
-            const CT g = L[c0 + r * kLX];
-            const CT dfx = (vxk != CT(0)) ? xface[tr * kXFaceStride + lx + 1] - xface[tr * kXFaceStride + lx] : CT(0);
-
-            // order-N equilibrium, shifted:  w_k [drho + rho P'(u)],
-            // P' = sum_{1 <= n+m <= N} a_n b_m with a_n = He_n(xi_i) ux^n / n!,
-            // b_m = He_m(xi_j) uy^m / m!, summed as C'_N + sum_n a_n (1 + C'_{N-n}),
-            // C'_r = b_1 + ... + b_r (no O(1) term, so no cancellation).
-            CT px[N + 1], py[N + 1];
-            px[1] = uxv[r];
-            py[1] = uyv[r];
-#pragma unroll
-            for (int n = 2; n <= N; ++n) {
-                px[n] = px[n - 1] * uxv[r];
-                py[n] = py[n - 1] * uyv[r];
-            }
-            CT cpre[N + 1];
-            cpre[0] = CT(0);
-#pragma unroll
-            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(hy[m], py[m], cpre[m - 1]);
-            CT pp = cpre[N];
-#pragma unroll
-            for (int n = 1; n <= N; ++n) pp = fmaT(hx[n] * px[n], CT(1) + cpre[N - n], pp);
-            const CT geq = wk * fmaT(p.rho0 + drho[r], pp, drho[r]);
-
-            const CT adv = fmaT(vxs, dfx, vys * dfy[r]);
-            const CT Lk = -fmaT(g - geq, inv_tau, adv);
-            CT res = fmaT(dt, Lk, g);
-            if (WITH_GN) {
-                CT b;
-                if constexpr (kDma)
-                    b = gnl[tr * kTX + lx];
-                else
-                    b = gnv[r];
-                res = fmaT(cb, res - b, b);
-            }
-            if (active(r)) store_from(out + k * P + node_off(r), res);
-        }
-
-        // d. next tile into the other LDS buffer, prefetch the one after
-        if constexpr (!kDma) {
-            if (k + 1 < p.K) {
-                stash(buf ^ 1, pre);
-                if (k + 2 < p.K) fetch(k + 2, pre);
-            }
-        }
-        __syncthreads();
-    }
+    fd_stage_tile<T, N, FIXED, WITH_GN>(src, gn, out, cb, p, d, blockIdx.x, blockIdx.y,
+                                        blockIdx.y * gridDim.x + blockIdx.x, DIAG);
 }
 
 template <typename T, int N, bool FIXED>

@@ -1,0 +1,486 @@
+// lb_server.cpp -- continuous batching of independent simulations (the
+// lb_server_* part of include/lb.h).
+//
+// A worker thread owns the device side.  It loops:
+//   1. admit queued requests (FIFO) while the slot count and the device-memory
+//      budget allow: create the simulation, upload and initialise its state;
+//   2. when the set of running simulations changed, rebuild the batch
+//      descriptors and the per-launch work lists (one entry per CS row or
+//      FD tile of every running simulation) and upload them;
+//   3. run a chunk of batched steps: per step one collision-streaming launch,
+//      three stage launches per finite-difference equilibrium order, and one
+//      launch that sums the diagnostics of the simulations sampled in that
+//      step; the chunk ends at the first completion (or after chunk_steps);
+//   4. drain the finished simulations: final diagnostics, series copied to
+//      the host, device memory released, result queued.
+// Requests that arrive meanwhile wait in the queue and are admitted at the
+// next chunk boundary, so new work overlaps with running work on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "lb.h"
+#include "lb_batch.h"
+#include "lb_sim_impl.h"
+
+using namespace lbm;
+
+namespace {
+
+struct Pending {
+    uint64_t id;
+    lb_request req;
+    double t_submit;
+    size_t footprint;
+};
+
+struct Running {
+    uint64_t id, tag;
+    lb_sim *sim;
+    int start_epoch, nsteps, every;
+    double t_submit, t_admit;
+    size_t footprint;
+    int N;  // FD equilibrium order (0 for CS)
+};
+
+// Device bytes a request will hold: state buffers, diagnostics partials and
+// output, probe vectors and the sample series (as allocated by lb_create,
+// lb_set_probe and lb_series_reserve).
+size_t footprint_of(const lb_request &r, const ModelInfo &mi)
+{
+    const bool cs = r.model == LB_CS_D2Q9;
+    const size_t nodes = (size_t)r.Nx * r.Ny;
+    const size_t state = (size_t)(cs ? 2 : 3) * mi.K * nodes * sizeof(float);
+    int blocks = std::max(cs_diag_blocks(r.Nx, r.Ny), fd_diag_blocks(r.Nx, r.Ny));
+    blocks = std::max(blocks, reduce_diag_blocks(r.Nx, r.Ny));
+    const size_t diag = sizeof(double) * kDiag * ((size_t)blocks + 1);
+    const size_t probe = 2 * (size_t)(r.Nx + r.Ny) * (sizeof(double) + sizeof(float));
+    const size_t series = sizeof(double) * kDiag * (size_t)(r.nsteps / r.sample_every + 2);
+    return state + diag + probe + series;
+}
+
+template <typename T>
+struct DevArray {
+    T *ptr = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap) return hipSuccess;
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+        const size_t want = std::max(n, cap * 2);
+        hipError_t e = hipMalloc(&ptr, want * sizeof(T));
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+    }
+};
+
+double now_s(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct lb_server {
+    size_t budget = 0;
+    int max_slots = 0;
+    int chunk = 0;
+    int device = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> queue;
+    std::deque<lb_result> done;
+    std::atomic<bool> stop{false};
+    std::thread worker;
+
+    // worker-owned state
+    std::vector<Running> running;
+    size_t used = 0;
+    hipStream_t stream = nullptr;
+    int epoch = 0;
+    DevArray<BatchSlot> d_slots;
+    DevArray<BatchWork> d_cs;
+    std::map<int, DevArray<BatchWork>> d_fd;  // per equilibrium order
+    std::map<int, int> n_fd;
+    int n_cs = 0;
+    DevArray<int> d_ids;
+
+    // counters (read under mu)
+    uint64_t next_id = 1;
+    double n_submitted = 0, n_completed = 0, steps_launched = 0, busy_s = 0;
+    size_t used_snapshot = 0;
+    int running_snapshot = 0;
+
+    void run();
+    int admit(const Pending &p);
+    int rebuild();
+    int run_chunk();
+    void drain();
+    void finish(uint64_t id, uint64_t tag, int status, double t_submit, double t_admit, std::vector<double> rows);
+};
+
+void lb_server::finish(uint64_t id, uint64_t tag, int status, double t_submit, double t_admit,
+                       std::vector<double> rows)
+{
+    lb_result r{};
+    r.id = id;
+    r.tag = tag;
+    r.status = status;
+    r.nsamples = (int)(rows.size() / 6);
+    r.samples = nullptr;
+    if (!rows.empty()) {
+        r.samples = static_cast<double *>(std::malloc(rows.size() * sizeof(double)));
+        if (r.samples)
+            std::memcpy(r.samples, rows.data(), rows.size() * sizeof(double));
+        else {
+            r.nsamples = 0;
+            r.status = LB_ENOMEM;
+        }
+    }
+    r.t_submit = t_submit;
+    r.t_admit = t_admit;
+    r.t_finish = now_s(t0);
+    std::lock_guard<std::mutex> lk(mu);
+    done.push_back(r);
+    n_completed += 1;
+    cv_done.notify_all();
+}
+
+int lb_server::admit(const Pending &p)
+{
+    const lb_request &q = p.req;
+    lb_sim *sim = lb_create(q.model | LB_FP32, q.Nx, q.Ny, q.tau, q.dt, q.ds, q.N);
+    if (!sim) return lb_last_error();
+    int rc = lb_set_stream(sim, stream);
+    if (rc == LB_OK) rc = lb_init(sim, q.rho, q.ux, q.uy);
+    if (rc == LB_OK && q.ax) rc = lb_set_probe(sim, q.ax, q.ay, q.bx, q.by);
+    if (rc == LB_OK) rc = lb_series_reserve(sim, q.nsteps / q.sample_every + 2);
+    if (rc != LB_OK) {
+        lb_destroy(sim);
+        return rc;
+    }
+    Running r{};
+    r.id = p.id;
+    r.tag = q.tag;
+    r.sim = sim;
+    r.start_epoch = epoch;
+    r.nsteps = q.nsteps;
+    r.every = q.sample_every;
+    r.t_submit = p.t_submit;
+    r.t_admit = now_s(t0);
+    r.footprint = p.footprint;
+    r.N = sim->cs ? 0 : sim->N;
+    running.push_back(r);
+    return LB_OK;
+}
+
+int lb_server::rebuild()
+{
+    const int n = (int)running.size();
+    std::vector<BatchSlot> slots(n);
+    std::vector<BatchWork> cs;
+    std::map<int, std::vector<BatchWork>> fd;
+    std::vector<int> ids(n);
+    for (int i = 0; i < n; ++i) {
+        lb_sim *s = running[i].sim;
+        BatchSlot &b = slots[i];
+        b.p = make_params<float>(s);
+        for (int j = 0; j < 3; ++j) b.buf[j] = static_cast<float *>(s->buf[j]);
+        b.partial = s->d_partial;
+        b.series = s->d_series;
+        if (s->probe) {
+            b.ax = s->d_probe32;
+            b.ay = s->d_probe32 + s->Nx;
+            b.bx = s->d_probe32 + s->Nx + s->Ny;
+            b.by = s->d_probe32 + 2 * s->Nx + s->Ny;
+        } else {
+            b.ax = b.ay = b.bx = b.by = nullptr;
+        }
+        b.model = s->cs ? 0 : 1;
+        b.start_epoch = running[i].start_epoch;
+        b.nsteps = running[i].nsteps;
+        b.every = running[i].every;
+        b.diag_blocks = diag_blocks_fused(s);
+        b.tiles_x = (s->Nx + 63) / 64;
+        ids[i] = i;
+        if (s->cs) {
+            for (int y = 0; y < s->Ny; ++y) cs.push_back({i, y});
+        } else {
+            const int tiles = fd_diag_blocks(s->Nx, s->Ny);
+            auto &v = fd[s->N];
+            for (int t = 0; t < tiles; ++t) v.push_back({i, t});
+        }
+    }
+    hipError_t e = d_slots.ensure(std::max(n, 1));
+    if (e == hipSuccess) e = d_ids.ensure(std::max(n, 1));
+    if (e == hipSuccess) e = d_cs.ensure(std::max<size_t>(cs.size(), 1));
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpyAsync(d_slots.ptr, slots.data(), n * sizeof(BatchSlot), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(d_ids.ptr, ids.data(), n * sizeof(int), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !cs.empty())
+        e = hipMemcpyAsync(d_cs.ptr, cs.data(), cs.size() * sizeof(BatchWork), hipMemcpyHostToDevice, stream);
+    n_cs = (int)cs.size();
+    n_fd.clear();
+    for (auto &kv : fd) {
+        if (e != hipSuccess) break;
+        auto &arr = d_fd[kv.first];
+        e = arr.ensure(kv.second.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(arr.ptr, kv.second.data(), kv.second.size() * sizeof(BatchWork), hipMemcpyHostToDevice,
+                               stream);
+        n_fd[kv.first] = (int)kv.second.size();
+    }
+    // the host vectors must outlive the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return dev_status(e);
+}
+
+int lb_server::run_chunk()
+{
+    int g = chunk;
+    for (const Running &r : running) g = std::min(g, r.nsteps - (epoch - r.start_epoch));
+    g = std::max(g, 1);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < g && e == hipSuccess; ++i) {
+        const int E = epoch + i;
+        e = launch_cs_batch(d_slots.ptr, d_cs.ptr, n_cs, E, stream);
+        for (auto &kv : n_fd) {
+            for (int stage = 1; stage <= 3 && e == hipSuccess; ++stage)
+                e = launch_fd_batch(d_slots.ptr, d_fd[kv.first].ptr, kv.second, kv.first, stage, E, stream);
+        }
+        if (e == hipSuccess) e = launch_finalize_batch(d_slots.ptr, d_ids.ptr, (int)running.size(), E, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    epoch += g;
+    std::lock_guard<std::mutex> lk(mu);
+    steps_launched += g;
+    return dev_status(e);
+}
+
+void lb_server::drain()
+{
+    std::vector<Running> keep;
+    for (Running &r : running) {
+        if (epoch - r.start_epoch < r.nsteps) {
+            keep.push_back(r);
+            continue;
+        }
+        lb_sim *s = r.sim;
+        // the batched steps advanced the handle's state
+        s->steps = r.nsteps;
+        if (s->cs) s->cur = r.nsteps & 1;
+        s->series_t.clear();
+        s->series_fused.clear();
+        for (int t = 0; t < r.nsteps; t += r.every) {
+            s->series_t.push_back(t);
+            s->series_fused.push_back(1);
+        }
+        std::vector<double> rows(6 * (s->series_t.size() + 1));
+        int got = lb_series_read(s, rows.data(), (int)s->series_t.size());
+        int status = got >= 0 ? LB_OK : got;
+        double fin[kDiag];
+        if (status == LB_OK) status = lb_reduce(s, fin);
+        if (status == LB_OK) {
+            rows.resize(6 * ((size_t)got + 1));
+            rows[6 * got] = (double)r.nsteps;
+            for (int j = 0; j < kDiag; ++j) rows[6 * got + 1 + j] = fin[j];
+        } else {
+            rows.clear();
+        }
+        lb_destroy(s);
+        used -= r.footprint;
+        finish(r.id, r.tag, status, r.t_submit, r.t_admit, std::move(rows));
+    }
+    running.swap(keep);
+}
+
+void lb_server::run()
+{
+    (void)hipSetDevice(device);
+    bool changed = false;
+    while (!stop.load()) {
+        std::vector<Pending> admit_now;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            while (!queue.empty() && (int)(running.size() + admit_now.size()) < max_slots &&
+                   used + queue.front().footprint <= budget) {
+                used += queue.front().footprint;
+                admit_now.push_back(queue.front());
+                queue.pop_front();
+            }
+            if (running.empty() && admit_now.empty()) {
+                used_snapshot = used;
+                running_snapshot = 0;
+                cv_work.wait_for(lk, std::chrono::milliseconds(5));
+                continue;
+            }
+        }
+        for (const Pending &p : admit_now) {
+            const int rc = admit(p);
+            if (rc != LB_OK) {
+                used -= p.footprint;
+                finish(p.id, p.req.tag, rc, p.t_submit, now_s(t0), {});
+            } else {
+                changed = true;
+            }
+        }
+        if (running.empty()) continue;
+        const double tb = now_s(t0);
+        int rc = LB_OK;
+        if (changed) rc = rebuild();
+        changed = false;
+        if (rc == LB_OK) rc = run_chunk();
+        if (rc != LB_OK) {
+            // a device error ends every running request
+            for (Running &r : running) {
+                lb_destroy(r.sim);
+                used -= r.footprint;
+                finish(r.id, r.tag, rc, r.t_submit, r.t_admit, {});
+            }
+            running.clear();
+            continue;
+        }
+        const size_t before = running.size();
+        drain();
+        if (running.size() != before) changed = true;
+        std::lock_guard<std::mutex> lk(mu);
+        busy_s += now_s(t0) - tb;
+        used_snapshot = used;
+        running_snapshot = (int)running.size();
+    }
+}
+
+extern "C" {
+
+lb_server *lb_server_create(size_t hbm_budget_bytes, int max_slots, int chunk_steps)
+{
+    if (hbm_budget_bytes == 0 || max_slots < 1 || max_slots > 4096 || chunk_steps < 1) {
+        set_last_error(LB_EINVAL);
+        return nullptr;
+    }
+    lb_server *s = new (std::nothrow) lb_server();
+    if (!s) {
+        set_last_error(LB_ENOMEM);
+        return nullptr;
+    }
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    s->chunk = chunk_steps;
+    s->t0 = std::chrono::steady_clock::now();
+    if (hipGetDevice(&s->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        set_last_error(LB_EDEVICE);
+        return nullptr;
+    }
+    s->worker = std::thread([s] { s->run(); });
+    return s;
+}
+
+int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
+{
+    if (!s || !req || !req->rho || !req->ux || !req->uy || req->nsteps < 1 || req->sample_every < 1 ||
+        (req->model & ~0xff) != 0)
+        return set_last_error(LB_EINVAL);
+    const bool probe_any = req->ax || req->ay || req->bx || req->by;
+    const bool probe_all = req->ax && req->ay && req->bx && req->by;
+    if (probe_any && !probe_all) return set_last_error(LB_EINVAL);
+    const int rc = validate_create(req->model | LB_FP32, req->Nx, req->Ny, req->tau, req->dt, req->ds, req->N);
+    if (rc != LB_OK) return set_last_error(rc);
+    ModelInfo mi{};
+    model_info(req->model, req->ds, req->dt, &mi);
+    Pending p{};
+    p.req = *req;
+    p.footprint = footprint_of(*req, mi);
+    if (p.footprint > s->budget) return set_last_error(LB_EBUSY);
+    std::lock_guard<std::mutex> lk(s->mu);
+    p.id = s->next_id++;
+    p.t_submit = now_s(s->t0);
+    s->queue.push_back(p);
+    s->n_submitted += 1;
+    s->cv_work.notify_all();
+    if (id) *id = p.id;
+    return LB_OK;
+}
+
+int lb_server_poll(lb_server *s, lb_result *out, int max, int timeout_us)
+{
+    if (!s || (max > 0 && !out) || max < 0) return set_last_error(LB_EINVAL);
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && timeout_us > 0)
+        s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [s] { return !s->done.empty(); });
+    int n = 0;
+    while (n < max && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    return n;
+}
+
+void lb_server_release(lb_server *, lb_result *res)
+{
+    if (!res) return;
+    std::free(res->samples);
+    res->samples = nullptr;
+    res->nsamples = 0;
+}
+
+double lb_server_clock(const lb_server *s) { return s ? now_s(s->t0) : -1.0; }
+
+int lb_server_stats(const lb_server *s, double out[7])
+{
+    if (!s || !out) return set_last_error(LB_EINVAL);
+    auto *m = const_cast<lb_server *>(s);
+    std::lock_guard<std::mutex> lk(m->mu);
+    out[0] = m->n_submitted;
+    out[1] = m->n_completed;
+    out[2] = (double)m->queue.size();
+    out[3] = (double)m->running_snapshot;
+    out[4] = (double)m->used_snapshot;
+    out[5] = m->steps_launched;
+    out[6] = m->busy_s;
+    return LB_OK;
+}
+
+void lb_server_destroy(lb_server *s)
+{
+    if (!s) return;
+    s->stop.store(true);
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
+    for (Running &r : s->running) lb_destroy(r.sim);
+    s->running.clear();
+    s->d_slots.release();
+    s->d_cs.release();
+    for (auto &kv : s->d_fd) kv.second.release();
+    s->d_ids.release();
+    for (lb_result &r : s->done) std::free(r.samples);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// lb_sim_impl.h -- the simulation handle behind the C ABI and the internal
+// helpers that the batch server (lb_server.cpp) shares with it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "lb.h"
+#include "lb_internal.h"
+#include "lb_model.h"
+
+namespace lbm {
+enum Prec { P32 = 0, P16 = 1, P64 = 2 };
+}  // namespace lbm
+
+struct lb_sim {
+    int model = 0;
+    lbm::Prec prec = lbm::P32;
+    bool cs = true;
+    int Nx = 0, Ny = 0, K = 0, Q = 0, N = 0;
+    double tau = 0, dt = 0, ds = 0;
+    lbm::ModelInfo mi{};
+    double rho0 = 1.0;
+    bool fixed = false;
+    double rho_l = 1.0, rho_r = 1.0;
+    double eps = 1e-6;
+    bool ready = false;
+    long long steps = 0;
+    int cur = 0;  // CS: buffer holding the current state
+    int pitch = 0, xoff = 0;
+    long long plane = 0;
+    size_t esize = 4;
+    int nbuf = 0;
+    void *buf[3] = {nullptr, nullptr, nullptr};
+    size_t buf_bytes = 0;
+    hipStream_t stream = nullptr, own_stream = nullptr;
+    double *d_partial = nullptr;  // per-block diagnostics partials
+    int partial_blocks = 0;
+    double *d_out = nullptr;      // kDiag doubles
+    bool probe = false;
+    double probe_den = 0.0;
+    double *d_probe64 = nullptr;  // ax | ay | bx | by
+    float *d_probe32 = nullptr;
+    double *d_series = nullptr;   // [series_cap][kDiag] raw sums
+    int series_cap = 0;
+    std::vector<long long> series_t;  // step index of each pending sample
+    std::vector<char> series_fused;   // sums in the step kernel's velocity unit
+};
+
+namespace lbm {
+
+int set_last_error(int code);
+// lb_create's parameter checks: LB_OK or the code lb_create would fail with
+int validate_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N);
+int state_index(const lb_sim *s);
+template <typename CT>
+Params<CT> make_params(const lb_sim *s);
+int dev_status(hipError_t e);
+int diag_blocks_fused(const lb_sim *s);
+void finish_diag(const lb_sim *s, const double *raw, double vscale, double *out);
+
+}  // namespace lbm

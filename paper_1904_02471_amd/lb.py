@@ -21,7 +21,9 @@ Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_F
 EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
            "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
-           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_stream", "lb_synchronize", "lb_device_bytes"]
+           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_stream", "lb_synchronize", "lb_device_bytes",
+           "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
+           "lb_server_stats", "lb_server_destroy"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p

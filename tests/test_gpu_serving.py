@@ -1,0 +1,109 @@
+"""The serving form: many simulations in one batched launch, admitted by
+memory footprint while others run.  Each result must be the same alone and
+in the mix, and the same as a single-simulation run of the same request."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_02471_amd import lb, serve, workloads
+
+pytestmark = pytest.mark.gpu
+
+EVERY = 10
+
+
+def small_mix():
+    """Seven requests of uneven size and model (the first is the probe)."""
+    t = [{"kind": "tgv", "side": 96, "model": "cs", "tau_std": 0.7, "steps": 57},
+         {"kind": "shear", "side": 64, "model": "fd16", "tau_std": 0.9, "steps": 33},
+         {"kind": "tgv", "side": 200, "model": "cs", "tau_std": 0.55, "steps": 121},
+         {"kind": "shear", "side": 128, "model": "cs", "tau_std": 1.3, "steps": 20},
+         {"kind": "tgv", "side": 130, "model": "fd16", "tau_std": 0.6, "steps": 45},
+         {"kind": "tgv", "side": 64, "model": "fd16", "tau_std": 1.1, "steps": 70},
+         {"kind": "shear", "side": 300, "model": "cs", "tau_std": 0.8, "steps": 64}]
+    return t
+
+
+def run_server(entries, budget=8 << 30, slots=64, chunk=16):
+    srv = serve.Server(budget, slots, chunk)
+    fields = serve.field_cache()
+    ids = []
+    for i, e in enumerate(entries):
+        kw = serve.trace_request(e, fields)
+        ids.append(srv.submit(sample_every=EVERY, tag=i, **kw))
+    res = serve.wait_all(srv, len(entries), 120)
+    srv.close()
+    by_tag = {r["tag"]: r for r in res}
+    for r in res:
+        assert r["status"] == 0, r
+    return [by_tag[i] for i in range(len(entries))]
+
+
+def single_run(e):
+    """The same request through the single-simulation path."""
+    kw = serve.trace_request(e, serve.field_cache())
+    g = lb.Sim(kw["model"], kw["Nx"], kw["Ny"], kw["tau"], kw["dt"], kw["ds"], kw["N"], precision=lb.LB_FP32)
+    g.init(kw["rho"], kw["ux"], kw["uy"])
+    g.set_probe(*kw["probe"])
+    g.series_reserve(kw["nsteps"] // EVERY + 2)
+    g.step_sampled(kw["nsteps"], EVERY)
+    rows = g.series_read()
+    final = np.concatenate([[kw["nsteps"]], g.reduce()])
+    return np.vstack([rows, final])
+
+
+def test_alone_equals_in_the_mix():
+    print("case: serving alone vs mix", flush=True)
+    mix = small_mix()
+    alone = run_server([mix[0]])[0]
+    together = run_server(mix)
+    assert np.array_equal(alone["samples"], together[0]["samples"])
+    # and every member of the mix equals its single-simulation run
+    for e, r in zip(mix, together):
+        ref = single_run(e)
+        assert r["samples"].shape == ref.shape, (e, r["samples"].shape, ref.shape)
+        assert np.array_equal(r["samples"], ref), e
+        assert r["t_finish"] >= r["t_admit"] >= r["t_submit"]
+
+
+def test_served_result_matches_oracle():
+    print("case: serving vs oracle", flush=True)
+    e = {"kind": "tgv", "side": 40, "model": "fd16", "tau_std": 0.8, "steps": 30}
+    c = {"kind": "shear", "side": 48, "model": "cs", "tau_std": 0.7, "steps": 40}
+    res = run_server([e, c])
+    for ent, r in zip([e, c], res):
+        kw = serve.trace_request(ent, serve.field_cache())
+        om = oracle.FD_D2Q16 if kw["model"] == lb.LB_FD_D2Q16 else oracle.CS_D2Q9
+        o = oracle.OracleSim(om, kw["Nx"], kw["Ny"], kw["tau"], kw["dt"], kw["ds"], kw["N"])
+        o.init(kw["rho"], kw["ux"], kw["uy"])
+        ax, ay, bx, by = kw["probe"]
+        px, py = np.outer(ay, ax), np.outer(by, bx)
+        o.step(kw["nsteps"])
+        want = o.reduce(px, py)
+        got = r["samples"][-1]
+        assert got[0] == kw["nsteps"]
+        assert got[1] == pytest.approx(want[0], rel=1e-6)
+        assert got[4] == pytest.approx(want[3], rel=1e-4)
+        assert got[5] == pytest.approx(want[4], rel=1e-5)
+
+
+def test_admission_by_memory_budget():
+    print("case: serving budget", flush=True)
+    entries = [{"kind": "tgv", "side": 256, "model": "cs", "tau_std": 0.7, "steps": 30 + 5 * i} for i in range(6)]
+    one = 2 * 9 * 256 * 256 * 4
+    res = run_server(entries, budget=int(1.5 * one) + (1 << 20), slots=64, chunk=8)
+    # only one simulation fits at a time: admissions follow completions
+    order = sorted(res, key=lambda r: r["t_admit"])
+    for a, b in zip(order, order[1:]):
+        assert b["t_admit"] >= a["t_finish"] - 1e-3
+    srv = serve.Server(1 << 20, 4, 8)
+    with pytest.raises(lb.LBError) as err:
+        kw = serve.trace_request(entries[0], serve.field_cache())
+        srv.submit(sample_every=EVERY, **kw)
+    assert err.value.code == lb.LB_EBUSY
+    with pytest.raises(lb.LBError) as err:
+        kw = serve.trace_request(entries[0], serve.field_cache())
+        kw["tau"] = 0.3   # negative viscosity
+        srv.submit(sample_every=EVERY, **kw)
+    assert err.value.code == lb.LB_EINVAL
+    srv.close()
