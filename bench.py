@@ -39,6 +39,8 @@ def parse():
                     help="time one model alone (profiling runs); the JSON line is then per model")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of the CS state size (counter calibration)")
+    ap.add_argument("--serving-requests", type=int, default=128,
+                    help="requests of the serving stream to replay (0: skip; 512: the whole stream)")
     return ap.parse_args()
 
 
@@ -92,6 +94,83 @@ def cpu_baseline(every):
             "sample": "FP64 C oracle, single thread: CS D2Q9 TGV 512x512 x 16 steps (%.3f MLUPS) + "
                       "FD D2Q16 TGV 256x256 x 4 steps (%.4f MLUPS), diagnostics every %d steps; value = "
                       "1 / (t_cs + t_fd) per node" % (1e-6 / t_cs, 1e-6 / t_fd, every)}
+
+
+def serving_bench(n_requests, every):
+    """Replay the first n_requests of the seeded serving stream (Poisson
+    arrivals, mean gap 2 ms; square grids 64..1024; CS D2Q9 or FD D2Q16;
+    500-5000 steps) twice on the GPU: batched (lb_server, continuous
+    batching) and one simulation per launch sequence (lb_sim per request, in
+    arrival order).  Reports sims/s and p50/p99 time-to-result (completion
+    minus arrival) for both, and whether every result is identical."""
+    import numpy as np
+
+    from paper_1904_02471_amd import lb, serve, workloads
+
+    trace = workloads.serving_trace(n_requests, 1904)
+    fields = serve.field_cache()
+    reqs = [serve.trace_request(e, fields) for e in trace]
+    n = len(trace)
+
+    # batched, continuous admission
+    srv = serve.Server(hbm_budget_bytes=200 << 30, max_slots=512, chunk_steps=32)
+    results = {}
+    t0 = time.perf_counter()
+    c0 = srv.clock()
+    k = 0
+    while len(results) < n:
+        now = time.perf_counter() - t0
+        while k < n and trace[k]["arrival_s"] <= now:
+            srv.submit(sample_every=every, tag=k, **reqs[k])
+            k += 1
+        for r in srv.poll(256, 500):
+            results[r["tag"]] = r
+            if len(results) % 64 == 0:
+                print("serving batched: %d/%d done at %.1f s" % (len(results), n, time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+    wall_b = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    lat_b = np.array([results[i]["t_finish"] - (c0 + trace[i]["arrival_s"]) for i in range(n)])
+    assert all(results[i]["status"] == 0 for i in range(n))
+
+    # one simulation per launch sequence
+    lat_s = np.zeros(n)
+    same = True
+    t0 = time.perf_counter()
+    for i, e in enumerate(trace):
+        while time.perf_counter() - t0 < e["arrival_s"]:
+            time.sleep(2e-4)
+        kw = reqs[i]
+        g = lb.Sim(kw["model"], kw["Nx"], kw["Ny"], kw["tau"], kw["dt"], kw["ds"], kw["N"], precision=lb.LB_FP32)
+        g.init(kw["rho"], kw["ux"], kw["uy"])
+        g.set_probe(*kw["probe"])
+        g.series_reserve(kw["nsteps"] // every + 2)
+        g.step_sampled(kw["nsteps"], every)
+        rows = g.series_read()
+        fin = np.concatenate([[kw["nsteps"]], g.reduce()])
+        g.destroy()
+        lat_s[i] = time.perf_counter() - t0 - e["arrival_s"]
+        same = same and np.array_equal(np.vstack([rows, fin]), results[i]["samples"])
+        if (i + 1) % 64 == 0:
+            print("serving one-by-one: %d/%d done at %.1f s" % (i + 1, n, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+    wall_s = time.perf_counter() - t0
+    nodes_steps = sum(kw["Nx"] * kw["Ny"] * kw["nsteps"] for kw in reqs)
+    return {
+        "requests": n, "stream": "seed 1904, Poisson arrivals mean 2 ms, side U{64..1024}, CS D2Q9 / FD D2Q16 "
+                                  "50/50, tau U[0.55,1.5], steps U{500..5000}, FP32, diagnostics every %d" % every,
+        "batched": {"sims_per_s": round(n / wall_b, 3), "wall_s": round(wall_b, 3),
+                    "p50_s": round(float(np.percentile(lat_b, 50)), 4),
+                    "p99_s": round(float(np.percentile(lat_b, 99)), 4),
+                    "mlups": round(nodes_steps / wall_b / 1e6, 1), "batch_steps": stats["batch_steps"]},
+        "one_sim_per_launch": {"sims_per_s": round(n / wall_s, 3), "wall_s": round(wall_s, 3),
+                               "p50_s": round(float(np.percentile(lat_s, 50)), 4),
+                               "p99_s": round(float(np.percentile(lat_s, 99)), 4),
+                               "mlups": round(nodes_steps / wall_s / 1e6, 1)},
+        "speedup_sims_per_s": round(wall_s / wall_b, 3),
+        "results_identical": bool(same),
+    }
 
 
 def main():
@@ -204,6 +283,10 @@ def main():
         ms = a.elapsed_time(b) / 20
         line["copy_calibration"] = {"bytes_moved": 2 * src.numel() * 4, "ms": round(ms, 5),
                                     "gbs": round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
+    if args.serving_requests > 0:
+        cs.destroy()
+        fd.destroy()
+        line["serving"] = serving_bench(args.serving_requests, every)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(every)
     print(json.dumps(line), flush=True)
