@@ -36,7 +36,9 @@ __global__ __launch_bounds__(kFdThreads) void fd_batch_kernel(const BatchSlot *_
                                                               const BatchWork *__restrict__ work, int epoch,
                                                               float cb)
 {
-    const BatchWork w = work[blockIdx.x];
+    // contiguous runs of the work list per XCD (workgroup b runs on XCD b % 8)
+    const int nb = gridDim.x, b = blockIdx.x, q = nb / 8, r = nb % 8, x = b % 8;
+    const BatchWork w = work[x * q + (x < r ? x : r) + b / 8];
     const BatchSlot &s = slots[w.slot];
     const int e = step_of(s, epoch);
     if (e < 0 || e >= s.nsteps) return;  // uniform over the workgroup

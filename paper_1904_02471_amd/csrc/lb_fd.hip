@@ -12,8 +12,14 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
                                                               const Params<typename Arith<T>::type> p,
                                                               const DiagArgs<typename Arith<T>::type> d)
 {
-    fd_stage_tile<T, N, FIXED, WITH_GN>(src, gn, out, cb, p, d, blockIdx.x, blockIdx.y,
-                                        blockIdx.y * gridDim.x + blockIdx.x, DIAG);
+    // Workgroups are dispatched round-robin over the 8 XCDs (block b to XCD
+    // b % 8).  Give each XCD a contiguous run of tiles (row-major), so that
+    // most halo cache lines are shared by tiles in the same XCD's L2.
+    const int nb = gridDim.x;
+    const int b = blockIdx.x, q = nb / 8, r = nb % 8, x = b % 8;
+    const int tile = x * q + (x < r ? x : r) + b / 8;
+    const int tiles_x = (p.Nx + kTX - 1) / kTX;
+    fd_stage_tile<T, N, FIXED, WITH_GN>(src, gn, out, cb, p, d, tile % tiles_x, tile / tiles_x, tile, DIAG);
 }
 
 template <typename T, int N, bool FIXED>
@@ -21,7 +27,7 @@ hipError_t launch_fd_n(const T *src, const T *gn, T *out, int stage, const Param
                        const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s)
 {
     using CT = typename Arith<T>::type;
-    dim3 grid((p.Nx + kTX - 1) / kTX, (p.Ny + kTY - 1) / kTY), block(kFdThreads);
+    dim3 grid(((p.Nx + kTX - 1) / kTX) * ((p.Ny + kTY - 1) / kTY)), block(kFdThreads);
     DiagArgs<CT> none{};
     if (stage == 1) {
         if (diag)
