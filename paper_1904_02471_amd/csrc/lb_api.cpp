@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -33,6 +34,58 @@ int fail(int code)
 namespace lbm {
 
 size_t elem_size(Prec p) { return p == P16 ? 2 : (p == P64 ? 8 : 4); }
+
+// CS D2Q9 constants in the arithmetic type, chosen so that the sums that
+// carry mass and momentum are exact as real numbers: w1 = fl(1/9), w5 = 1/36
+// rounded to a quarter of w0's ulp, w0 = 1 - 4 w1 - 4 w5 (representable by
+// construction); a1 = fl(1/3), a5 = (1 - 2 a1) / 4 (representable).  Each
+// differs from its exact value by at most about one ulp.
+template <typename CT>
+void cs_exact_constants(Params<CT> &p)
+{
+    constexpr int digits = std::numeric_limits<CT>::digits;
+    const long double q = std::ldexp(1.0L, -3 - digits);  // w0 in [1/4, 1/2): ulp 2^(-1-digits)
+    const CT w1 = (CT)(1.0L / 9.0L);
+    const CT w5 = (CT)(std::nearbyint((1.0L / 36.0L) / q) * q);
+    const CT w0 = (CT)(1.0L - 4.0L * w1 - 4.0L * w5);
+    const CT a1 = (CT)(1.0L / 3.0L);
+    const CT a5 = (CT)((1.0L - 2.0L * a1) / 4.0L);
+    p.cs_w0 = w0;
+    p.cs_w1 = w1;
+    p.cs_w5 = w5;
+    p.cs_a1 = a1;
+    p.cs_a5 = a5;
+}
+
+// Mass and momentum defects of the FD equilibrium tables as stored in the
+// arithmetic type (Section 1: the quadrature reproduces the Hermite moments
+// exactly, so every one of these sums vanishes for exact constants).  The
+// products of stored constants are formed in long double.
+template <typename CT>
+void fd_moment_defects(Params<CT> &p)
+{
+    long double W = 0.0L;
+    for (int k = 0; k < p.K; ++k) W += (long double)p.w[k];
+    p.fd_w1 = (CT)(W - 1.0L);
+    for (int n = 0; n <= kMaxN; ++n)
+        for (int m = 0; m <= kMaxN; ++m) {
+            long double sm = 0.0L, sx = 0.0L, sy = 0.0L;
+            if (n + m <= p.N) {
+                for (int k = 0; k < p.K; ++k) {
+                    const long double t = (long double)p.w[k] * (long double)p.hc[p.ki[k]][n] *
+                                          (long double)p.hc[p.kj[k]][m];
+                    sm += t;
+                    sx += t * (long double)p.vx[k];
+                    sy += t * (long double)p.vy[k];
+                }
+                if (n == 1 && m == 0) sx -= 1.0L;  // c_s = 1 in FD units
+                if (n == 0 && m == 1) sy -= 1.0L;
+            }
+            p.fd_m[n][m] = (n + m == 0) ? CT(0) : (CT)sm;
+            p.fd_jx[n][m] = (CT)sx;
+            p.fd_jy[n][m] = (CT)sy;
+        }
+}
 
 template <typename CT>
 Params<CT> make_params(const lb_sim *s)
@@ -66,6 +119,10 @@ Params<CT> make_params(const lb_sim *s)
     }
     for (int i = 0; i < s->Q; ++i)
         for (int n = 0; n <= kMaxN; ++n) p.hc[i][n] = (CT)s->mi.hc[i][n];
+    if (s->cs)
+        cs_exact_constants(p);
+    else
+        fd_moment_defects(p);
     return p;
 }
 

@@ -53,9 +53,10 @@ __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict_
     const T *rn = src + (long long)yp * p.pitch + p.xoff;  // row y+1: sources of S, SW, SE
     T *o = dst + (long long)y * p.pitch + p.xoff;
 
-    const CT w0 = p.w[0], w1 = p.w[1], w5 = p.w[5];
+    const CT w0 = p.cs_w0, w1 = p.cs_w1, w5 = p.cs_w5, a1 = p.cs_a1, a5 = p.cs_a5;
+    const CT b1 = CT(0.5), b5 = CT(0.125);  // 4.5 w, exact
     const CT omega = p.omega, rho0 = p.rho0;
-    const CT c3 = CT(3), c45 = CT(4.5), c15 = CT(1.5);
+    const CT c15 = CT(1.5);
 
     DiagAcc acc;
     CT pay = CT(0), pby = CT(0);
@@ -93,20 +94,29 @@ __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict_
         const CT ux = jx * inv, uy = jy * inv;
         const CT usq = c15 * cs_fma(ux, ux, uy * uy);
 
-        // second-order equilibrium, shifted: w_k [drho + rho (3 eu + 4.5 eu^2 - 1.5 u^2)]
-        auto relax = [&](CT g, CT w, CT eu) -> CT {
-            const CT geq = w * cs_fma(rho, cs_fma(eu, cs_fma(c45, eu, c3), -usq), drho);
+        // second-order equilibrium, shifted, written as
+        //   w_k drho + a_k (e_k . j) + rho (b_k (e_k . u)^2 - w_k 1.5 u^2),
+        // a = 3 w, b = 4.5 w: the first-order term takes j itself (rho * (j / rho)
+        // would carry the quotient's rounding into the momentum every step), and
+        // with the constants' exact sums the mass and momentum of the
+        // equilibrium equal the node's up to unbiased rounding.
+        auto relax = [&](CT g, CT w, CT a, CT b, CT ej, CT eu) -> CT {
+            const CT sec = rho * cs_fma(b * eu, eu, -(w * usq));
+            const CT geq = cs_fma(w, drho, cs_fma(a, ej, sec));
             return cs_fma(omega, geq - g, g);
         };
-        store_from(o + x, relax(g0, w0, CT(0)));
-        store_from(o + 1 * P + x, relax(g1, w1, ux));
-        store_from(o + 2 * P + x, relax(g2, w1, uy));
-        store_from(o + 3 * P + x, relax(g3, w1, -ux));
-        store_from(o + 4 * P + x, relax(g4, w1, -uy));
-        store_from(o + 5 * P + x, relax(g5, w5, ux + uy));
-        store_from(o + 6 * P + x, relax(g6, w5, uy - ux));
-        store_from(o + 7 * P + x, relax(g7, w5, -ux - uy));
-        store_from(o + 8 * P + x, relax(g8, w5, ux - uy));
+        {
+            const CT geq0 = cs_fma(w0, drho, -(rho * (w0 * usq)));
+            store_from(o + x, cs_fma(omega, geq0 - g0, g0));
+        }
+        store_from(o + 1 * P + x, relax(g1, w1, a1, b1, jx, ux));
+        store_from(o + 2 * P + x, relax(g2, w1, a1, b1, jy, uy));
+        store_from(o + 3 * P + x, relax(g3, w1, a1, b1, -jx, -ux));
+        store_from(o + 4 * P + x, relax(g4, w1, a1, b1, -jy, -uy));
+        store_from(o + 5 * P + x, relax(g5, w5, a5, b5, jx + jy, ux + uy));
+        store_from(o + 6 * P + x, relax(g6, w5, a5, b5, jy - jx, uy - ux));
+        store_from(o + 7 * P + x, relax(g7, w5, a5, b5, -jx - jy, -ux - uy));
+        store_from(o + 8 * P + x, relax(g8, w5, a5, b5, jx - jy, ux - uy));
 
         if (FIXED) {
             // the next step pulls E, NE, SE into x = 0 from column -1 and W,

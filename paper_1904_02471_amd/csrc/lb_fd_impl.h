@@ -126,6 +126,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     // global memory straight into LDS (global_load_lds), without registers
     constexpr bool kDma = std::is_same<T, float>::value;
     __shared__ CT gnl[kDma && WITH_GN ? kTY * kTX : 1];
+    __shared__ CT dltl[kRows * kFdThreads];  // per node: mass defect of the tables / rho
 
     const int tid = threadIdx.x;
     const int lx = tid & 63, wy = tid >> 6;
@@ -245,6 +246,49 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             }
         }
         if (diag) block_diag_store(acc, d.partial, diag_block);
+
+        // Moment-exact equilibrium.  The rounded tables give the equilibrium
+        // mass and momentum defects of relative size ~1e-8 (polynomials in u
+        // whose coefficients are exact sums in Params); left alone they act
+        // every stage with the same sign and drift the FP32 state.  They are
+        // removed here, once per node, inside operations whose exact results
+        // are not yet rounded: subtracting a correction below half an ulp from
+        // an already rounded smooth field would round it away or double it in
+        // a fixed spatial pattern.  u: one Newton step on rho u = j, with the
+        // momentum defect rho (ex, ey) folded into the residual, so that
+        // rho * u reproduces j - defect rather than rho * fl(j / rho).  Mass:
+        // defect / rho enters the equilibrium sum P' as its starting value
+        // (kept in LDS, thread-private, to spare registers).  By symmetry of the tables only even-even (mass), odd-even (x)
+        // and even-odd (y) monomials remain.
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const CT ux = uxv[r], uy = uyv[r];
+            CT xp[N + 1], yp[N + 1];
+            xp[0] = yp[0] = CT(1);
+#pragma unroll
+            for (int n = 1; n <= N; ++n) {
+                xp[n] = xp[n - 1] * ux;
+                yp[n] = yp[n - 1] * uy;
+            }
+            CT dm = CT(0), ex = CT(0), ey = CT(0);
+#pragma unroll
+            for (int n = 0; n <= N; ++n)
+#pragma unroll
+                for (int m = 0; n + m <= N; ++m) {
+                    if (n % 2 == 0 && m % 2 == 0 && n + m > 0) dm = fmaT(p.fd_m[n][m], xp[n] * yp[m], dm);
+                    if (n % 2 == 1 && m % 2 == 0) {
+                        ex = fmaT(p.fd_jx[n][m], xp[n] * yp[m], ex);
+                        ey = fmaT(p.fd_jy[m][n], xp[m] * yp[n], ey);
+                    }
+                }
+            const CT rho = p.rho0 + drho[r];  // the same value the node update forms
+            const CT inv = CT(1) / rho;
+            const CT rx = fmaT(-rho, ex, fmaT(-rho, ux, jx[r]));
+            const CT ry = fmaT(-rho, ey, fmaT(-rho, uy, jy[r]));
+            uxv[r] = fmaT(rx, inv, ux);
+            uyv[r] = fmaT(ry, inv, uy);
+            dltl[r * kFdThreads + tid] = fmaT(p.fd_w1 * drho[r], inv, dm);
+        }
     }
 
     const CT eps = p.eps, dt = p.dt, inv_tau = p.inv_tau;
@@ -356,7 +400,14 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             // order-N equilibrium, shifted:  w_k [drho + rho P'(u)],
             // P' = sum_{1 <= n+m <= N} a_n b_m with a_n = He_n(xi_i) ux^n / n!,
             // b_m = He_m(xi_j) uy^m / m!, summed as C'_N + sum_n a_n (1 + C'_{N-n}),
-            // C'_r = b_1 + ... + b_r (no O(1) term, so no cancellation).
+            // C'_r = b_1 + ... + b_r (no O(1) term, so no cancellation) less the
+            // mass defect per unit rho.  The terms odd and even in xi_j (in the
+            // prefix sums) and in xi_i (in the a_n sum) are accumulated apart
+            // and joined last: mirrored populations then share their even part
+            // bit for bit, and the roundings of the mass they carry do not
+            // drift one way (a single running sum rounds the small even terms
+            // against a large odd one, with a bias of ~10% of the rounding
+            // noise in D2Q36).
             CT px[N + 1], py[N + 1];
             px[1] = uxv[r];
             py[1] = uyv[r];
@@ -365,13 +416,25 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 px[n] = px[n - 1] * uxv[r];
                 py[n] = py[n - 1] * uyv[r];
             }
-            CT cpre[N + 1];
-            cpre[0] = CT(0);
+            CT ce = -dltl[r * kFdThreads + tid], co = CT(0);
+            CT cp[N];  // C'_0 .. C'_{N-1}
+            cp[0] = ce;
 #pragma unroll
-            for (int m = 1; m <= N; ++m) cpre[m] = fmaT(hy[m], py[m], cpre[m - 1]);
-            CT pp = cpre[N];
+            for (int m = 1; m <= N; ++m) {
+                if (m % 2)
+                    co = fmaT(hy[m], py[m], co);
+                else
+                    ce = fmaT(hy[m], py[m], ce);
+                if (m < N) cp[m] = ce + co;
+            }
 #pragma unroll
-            for (int n = 1; n <= N; ++n) pp = fmaT(hx[n] * px[n], CT(1) + cpre[N - n], pp);
+            for (int n = N; n >= 1; --n) {
+                if (n % 2)
+                    co = fmaT(hx[n] * px[n], CT(1) + cp[N - n], co);
+                else
+                    ce = fmaT(hx[n] * px[n], CT(1) + cp[N - n], ce);
+            }
+            const CT pp = ce + co;
             const CT geq = wk * fmaT(p.rho0 + drho[r], pp, drho[r]);
 
             const CT adv = fmaT(vxs, dfx, vys * dfy[r]);

@@ -37,6 +37,17 @@ struct Params {
     int ki[kMaxK], kj[kMaxK];     // per-axis root index of population k
     CT ghost_l[kMaxK], ghost_r[kMaxK];  // stored end equilibria: w_k (rho_end - rho0)
     CT hc[kMaxQ][kMaxN + 1];      // He_n(xi_i) / n!, xi_i = root i in units of c_s
+    // CS D2Q9 equilibrium constants chosen so that, as exact real numbers,
+    // w0 + 4 w1 + 4 w5 = 1 and 2 a1 + 4 a5 = 1 (a = 3 w): the equilibrium then
+    // carries exactly the node's mass and momentum up to unbiased rounding.
+    CT cs_w0, cs_w1, cs_w5, cs_a1, cs_a5;
+    // FD: moment defects of the rounded tables, as exact sums over k of the
+    // stored constants: mass  sum_k w_k hc[i_k][n] hc[j_k][m]       (fd_m),
+    // momentum  sum_k w_k v_k hc[i_k][n] hc[j_k][m] - delta (fd_jx, fd_jy),
+    // and fd_w1 = sum_k w_k - 1.  Zero in exact arithmetic; the stage kernel
+    // removes them from its equilibrium node by node.
+    CT fd_w1;
+    CT fd_m[kMaxN + 1][kMaxN + 1], fd_jx[kMaxN + 1][kMaxN + 1], fd_jy[kMaxN + 1][kMaxN + 1];
 };
 
 // Fused or stand-alone diagnostics: per-block FP64 partial sums.
