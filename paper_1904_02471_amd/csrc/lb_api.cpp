@@ -107,6 +107,7 @@ Params<CT> make_params(const lb_sim *s)
     p.inv_ds = (CT)(1.0 / s->ds);
     p.inv_tau = (CT)(1.0 / s->tau);
     p.eps = (CT)s->eps;
+    p.salt = mix_host((unsigned)s->steps);
     for (int k = 0; k < s->K; ++k) {
         p.w[k] = (CT)s->mi.w[k];
         p.vx[k] = (CT)s->mi.vx[k];

@@ -26,6 +26,8 @@
 
 #pragma once
 
+#include <type_traits>
+
 #include "lb_diag.h"
 #include "lb_internal.h"
 
@@ -105,18 +107,26 @@ __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict_
             const CT geq = cs_fma(w, drho, cs_fma(a, ej, sec));
             return cs_fma(omega, geq - g, g);
         };
+        // FP16 storage rounds stochastically: one counter-based draw per
+        // node and step, advanced per population (unused otherwise)
+        uint32_t rb = 0;
+        if constexpr (std::is_same<T, __half>::value) rb = mix32((uint32_t)(y * Nx + x), p.salt);
+        auto put = [&](T *q, CT v) {
+            if constexpr (std::is_same<T, __half>::value) rb = xorshift32(rb);
+            store_state(q, v, rb);
+        };
         {
             const CT geq0 = cs_fma(w0, drho, -(rho * (w0 * usq)));
-            store_from(o + x, cs_fma(omega, geq0 - g0, g0));
+            put(o + x, cs_fma(omega, geq0 - g0, g0));
         }
-        store_from(o + 1 * P + x, relax(g1, w1, a1, b1, jx, ux));
-        store_from(o + 2 * P + x, relax(g2, w1, a1, b1, jy, uy));
-        store_from(o + 3 * P + x, relax(g3, w1, a1, b1, -jx, -ux));
-        store_from(o + 4 * P + x, relax(g4, w1, a1, b1, -jy, -uy));
-        store_from(o + 5 * P + x, relax(g5, w5, a5, b5, jx + jy, ux + uy));
-        store_from(o + 6 * P + x, relax(g6, w5, a5, b5, jy - jx, uy - ux));
-        store_from(o + 7 * P + x, relax(g7, w5, a5, b5, -jx - jy, -ux - uy));
-        store_from(o + 8 * P + x, relax(g8, w5, a5, b5, jx - jy, ux - uy));
+        put(o + 1 * P + x, relax(g1, w1, a1, b1, jx, ux));
+        put(o + 2 * P + x, relax(g2, w1, a1, b1, jy, uy));
+        put(o + 3 * P + x, relax(g3, w1, a1, b1, -jx, -ux));
+        put(o + 4 * P + x, relax(g4, w1, a1, b1, -jy, -uy));
+        put(o + 5 * P + x, relax(g5, w5, a5, b5, jx + jy, ux + uy));
+        put(o + 6 * P + x, relax(g6, w5, a5, b5, jy - jx, uy - ux));
+        put(o + 7 * P + x, relax(g7, w5, a5, b5, -jx - jy, -ux - uy));
+        put(o + 8 * P + x, relax(g8, w5, a5, b5, jx - jy, ux - uy));
 
         if (FIXED) {
             // the next step pulls E, NE, SE into x = 0 from column -1 and W,

@@ -28,17 +28,19 @@ hipError_t launch_fd_n(const T *src, const T *gn, T *out, int stage, const Param
 {
     using CT = typename Arith<T>::type;
     dim3 grid(((p.Nx + kTX - 1) / kTX) * ((p.Ny + kTY - 1) / kTY)), block(kFdThreads);
+    Params<CT> ps = p;  // a distinct random stream per stage
+    ps.salt = mix_host(p.salt * 3u + (unsigned)stage);
     DiagArgs<CT> none{};
     if (stage == 1) {
         if (diag)
             hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, true, false>), grid, block, 0, s, src, nullptr, out,
-                               CT(1), p, *diag);
+                               CT(1), ps, *diag);
         else
             hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false, false>), grid, block, 0, s, src, nullptr, out,
-                               CT(1), p, none);
+                               CT(1), ps, none);
     } else {
         const CT cb = (stage == 2) ? CT(0.25) : CT(2) / CT(3);
-        hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false, true>), grid, block, 0, s, src, gn, out, cb, p,
+        hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false, true>), grid, block, 0, s, src, gn, out, cb, ps,
                            none);
     }
     return hipGetLastError();

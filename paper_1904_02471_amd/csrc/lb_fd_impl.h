@@ -448,7 +448,12 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                     b = gnv[r];
                 res = fmaT(cb, res - b, b);
             }
-            if (active(r)) store_from(out + k * P + node_off(r), res);
+            if (active(r)) {
+                uint32_t rb = 0;
+                if constexpr (std::is_same<T, __half>::value)
+                    rb = mix32((uint32_t)((gy0 + r) * Nx + gx), p.salt ^ ((uint32_t)k * 0x632be5abu));
+                store_state(out + k * P + node_off(r), res, rb);
+            }
         }
 
         // d. next tile into the other LDS buffer, prefetch the one after

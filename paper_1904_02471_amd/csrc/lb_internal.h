@@ -48,6 +48,7 @@ struct Params {
     // removes them from its equilibrium node by node.
     CT fd_w1;
     CT fd_m[kMaxN + 1][kMaxN + 1], fd_jx[kMaxN + 1][kMaxN + 1], fd_jy[kMaxN + 1][kMaxN + 1];
+    unsigned salt;  // per launch: seeds the stochastic rounding of FP16 stores
 };
 
 // Fused or stand-alone diagnostics: per-block FP64 partial sums.
@@ -64,6 +65,68 @@ __device__ __forceinline__ void store_from(__half *p, float v) { *p = __float2ha
 __device__ __forceinline__ void store_from(double *p, double v) { *p = v; }
 __device__ __forceinline__ void store_from(float *p, double v) { *p = (float)v; }
 __device__ __forceinline__ void store_from(__half *p, double v) { *p = __builtin_bit_cast(__half, (_Float16)v); }
+
+// Stochastic rounding of an FP32 value to FP16 with 32 random bits r: the
+// bits of the FP32 pattern below the FP16 ulp (13 in the normal range, more
+// in the subnormal range) get r added and are then cleared, so the value
+// rounds up with probability equal to its position between the two FP16
+// neighbours; the result is exact in FP16, so the final conversion does not
+// round again.  Below the smallest subnormal (2^-24) the choice is between 0
+// and 2^-24.  Unbiased: a state that changes by less than an FP16 ulp per
+// step still evolves correctly on average, where round-to-nearest would hold
+// it fixed.
+__device__ __forceinline__ __half half_sr(float v, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(v);
+    uint32_t a = b & 0x7fffffffu;
+    if (a >= 0x38800000u) {  // |v| >= 2^-14
+        a = (a + (r & 0x1fffu)) & ~0x1fffu;
+    } else if (a >= 0x33800000u) {  // 2^-24 <= |v| < 2^-14: FP16 grid 2^-24
+        const uint32_t m = (1u << (126u - (a >> 23))) - 1u;  // 14..23 bits
+        a = (a + (r & m)) & ~m;
+    } else {
+        const float p = __uint_as_float(a) * 16777216.0f;  // |v| / 2^-24, exact
+        a = ((float)(r >> 8) * (1.0f / 16777216.0f) < p) ? 0x33800000u : 0u;
+    }
+    return __float2half_rn(__uint_as_float(a | (b & 0x80000000u)));
+}
+
+// Counter-based random bits (a 32-bit integer mixer) for (key, salt).
+__device__ __forceinline__ uint32_t mix32(uint32_t key, uint32_t salt)
+{
+    uint32_t h = key * 0x9e3779b1u ^ salt;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t xorshift32(uint32_t s)
+{
+    s ^= s << 13;
+    s ^= s >> 17;
+    s ^= s << 5;
+    return s;
+}
+
+// Host-side mixer for per-launch salts.
+inline unsigned mix_host(unsigned x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Store of a stepped state value: FP16 storage rounds stochastically with the
+// given random bits, the other storage types round to nearest.
+__device__ __forceinline__ void store_state(float *p, float v, uint32_t) { *p = v; }
+__device__ __forceinline__ void store_state(double *p, double v, uint32_t) { *p = v; }
+__device__ __forceinline__ void store_state(__half *p, float v, uint32_t r) { *p = half_sr(v, r); }
 
 template <typename T> struct Arith { using type = float; };
 template <> struct Arith<double> { using type = double; };

@@ -238,8 +238,14 @@ def test_uniform_state_stays_uniform_and_rest_is_exact():
         g.init(np.full((30, 40), 1.03), np.full((30, 40), 0.02), np.full((30, 40), -0.01))
         g.step(20)
         f = g.get_state()
+        # stochastic rounding (FP16): uniform in distribution, every value
+        # within a few FP16 ulps of the largest stored (shifted) magnitude
+        gmax = max(abs(f[k].mean() - g.w[k] * 1.03) for k in range(9))  # rho0 = 1.03
         for k in range(9):
-            assert np.all(f[k] == f[k, 0, 0])
+            if prec == lb.LB_FP16_SHIFTED:
+                assert np.abs(f[k] - f[k].mean()).max() <= 8 * 2.0 ** -11 * gmax
+            else:
+                assert np.all(f[k] == f[k, 0, 0])
         # rho = rho0, u = 0: the shifted state is exactly zero and stays so
         g.init(np.ones((30, 40)), np.zeros((30, 40)), np.zeros((30, 40)))
         g.step(10)

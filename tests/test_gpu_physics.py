@@ -143,13 +143,19 @@ def test_taylor_green_4096_fp32():
     assert nu_fit == pytest.approx(nu, rel=1e-3)
 
 
-@pytest.mark.skip(reason="FP16 round-to-nearest storage holds the slowly decaying "
-                  "4096^2 vortex frozen between ulps (fitted nu 15% off)")
 def test_taylor_green_4096_fp16():
+    """FP16-shifted storage with stochastic rounding.  The vortex decays by
+    4e-4 over the run, ~8e-8 per step, while one FP16 ulp of the stored
+    populations is ~5e-4 of them: round-to-nearest freezes the state between
+    ulps (fitted nu 15% off).  Stochastic rounding is unbiased, and what is
+    left is its noise: ~1e-6 of momentum per node and step, which projects
+    onto the vortex as a random walk whose least-squares slope error is a few
+    1e-3 of the decay rate over 5000 steps.  Bound: 5e-3 (the FP32 storage
+    case above meets 1e-3)."""
     print("case: tgv 4096 fp16", flush=True)
     nu_fit, nu = tgv4096_nu(lb.LB_FP16_SHIFTED)
     print("nu fp16 %.7f analytic %.7f" % (nu_fit, nu), flush=True)
-    assert nu_fit == pytest.approx(nu, rel=1e-3)
+    assert nu_fit == pytest.approx(nu, rel=5e-3)
 
 
 def test_taylor_green_2048_fd_d2q36():
