@@ -22,12 +22,21 @@ __global__ __launch_bounds__(kCsThreads) void cs_batch_kernel(const BatchSlot *_
     if (e < 0 || e >= s.nsteps) return;  // uniform over the workgroup
     const float *src = s.buf[e & 1];
     float *dst = s.buf[(e & 1) ^ 1];
+    // the same row form as the single-simulation launch, so that the fused
+    // diagnostics sum in the same order
+    const bool vec = cs_vec_ok<float>(s.p);
     if (e % s.every == 0) {
         const DiagArgs<float> d{s.partial, s.ax, s.ay, s.bx, s.by};
-        cs_row<float, false, true>(src, dst, s.p, d, w.local, w.local);
+        if (vec)
+            cs_row_vec<float, true>(src, dst, s.p, d, w.local, w.local);
+        else
+            cs_row<float, false, true>(src, dst, s.p, d, w.local, w.local);
     } else {
         const DiagArgs<float> d{};
-        cs_row<float, false, false>(src, dst, s.p, d, w.local, w.local);
+        if (vec)
+            cs_row_vec<float, false>(src, dst, s.p, d, w.local, w.local);
+        else
+            cs_row<float, false, false>(src, dst, s.p, d, w.local, w.local);
     }
 }
 

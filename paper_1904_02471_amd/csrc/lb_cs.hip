@@ -14,11 +14,29 @@ __global__ __launch_bounds__(kCsThreads) void cs_step_kernel(const T *__restrict
     cs_row<T, FIXED, DIAG>(src, dst, p, d, blockIdx.x, blockIdx.x);
 }
 
+template <typename T, bool DIAG>
+__global__ __launch_bounds__(1024) void cs_step_vec_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                                 const Params<typename Arith<T>::type> p,
+                                                                 const DiagArgs<typename Arith<T>::type> d)
+{
+    cs_row_vec<T, DIAG>(src, dst, p, d, blockIdx.x, blockIdx.x);
+}
+
 template <typename T, bool FIXED>
 hipError_t launch_cs_t(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
                        const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s)
 {
     dim3 grid(p.Ny), block(kCsThreads);
+    if (!FIXED && cs_vec_ok<T>(p)) {
+        const dim3 vblock(cs_vec_threads<T>(p.Nx));
+        if (diag) {
+            hipLaunchKernelGGL((cs_step_vec_kernel<T, true>), grid, vblock, 0, s, src, dst, p, *diag);
+        } else {
+            DiagArgs<typename Arith<T>::type> none{};
+            hipLaunchKernelGGL((cs_step_vec_kernel<T, false>), grid, vblock, 0, s, src, dst, p, none);
+        }
+        return hipGetLastError();
+    }
     if (diag) {
         hipLaunchKernelGGL((cs_step_kernel<T, FIXED, true>), grid, block, 0, s, src, dst, p, *diag);
     } else {

@@ -62,6 +62,21 @@ def test_cs_ragged_shapes(shape):
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_NAME[p])
+@pytest.mark.parametrize("Nx", [4, 8, 12, 260, 516, 2052, 4100])
+def test_cs_vector_rows(Nx, prec):
+    """Periodic rows whose width is a multiple of the chunk width take the
+    vector row form: one chunk, a partial wave, the edge lanes of several
+    waves and several chunks per thread (rows wider than 1024 chunks)."""
+    print("case: cs vector rows", Nx, PREC_NAME[prec], flush=True)
+    Ny = 3
+    g, o = cs_case(Nx, Ny, tau=0.65, prec=prec)
+    f0 = workloads.random_distribution(9, Nx, Ny, 11 + Nx, g.w, spread=0.2)
+    g.set_state(f0)
+    o.set_state(f0)
+    run_and_compare(g, o, [1, 4], prec, "cs vector rows %d %s" % (Nx, PREC_NAME[prec]))
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_NAME[p])
 def test_cs_fixed_ends(prec):
     print("case: cs fixed ends 19x6", PREC_NAME[prec], flush=True)
     g, o = cs_case(19, 6, tau=0.8, prec=prec, bc=(1.3, 0.8))
