@@ -25,6 +25,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# FP32 vector peak without packed FP32 instructions (the library is built
+# without them): 256 CUs x 64 lanes x 2 flop per fma x 2.4 GHz.  The
+# published 157.3 TFLOP/s counts packed (two-wide) FP32 instructions.
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+VALU_PEAK_PUBLISHED_TFLOPS = 157.3
+# Algorithmic flops of the FD D2Q16 (N = 3) stage, fma counted as 2: per
+# node and population the x- and y-face WENO-5 values (47 each, with the
+# second differences, smoothness terms and first differences of a cell
+# shared by its two faces), the two flux differences (2), the order-3
+# equilibrium (29) and the stage update (8 in stage 1, 11 with the
+# Runge-Kutta combination of stages 2 and 3); per node the moments of 16
+# populations (80) and the moment-exact equilibrium corrections (40).
+FD16_FLOPS_NODE_POP = (2 * 47 + 2 + 29 + 8, 2 * 47 + 2 + 29 + 11, 2 * 47 + 2 + 29 + 11)
+FD16_FLOPS_NODE = 120
 
 
 def parse():
@@ -63,6 +77,30 @@ def make_sims(lb, workloads, units, n, stream):
     fd.init(r, ux, uy)
     fd.set_probe(ax, ay, bx, by)
     return cs, fd, {"tau_fd": tau_fd, "dt_fd": dt_fd}
+
+
+def source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1904_02471_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_traffic(kernel, n):
+    """HBM bytes per launch of `kernel` on the n x n workload from the
+    calibrated FETCH_SIZE + WRITE_SIZE counters recorded in
+    paper_1904_02471_amd/kernel_traffic.json, or None when none were recorded
+    for this workload or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "paper_1904_02471_amd", "kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec or rec.get("grid") != [n, n] or rec.get("sources_sha256") != source_digest(rec["sources"]):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(every):
@@ -266,10 +304,22 @@ def main():
                      "mlups": round(nodes / (fd_ms * 1e-3) / 1e6, 1) if run_fd else None,
                      "achieved_gbs_stagewise": round(fd_gbs, 1), "hbm_frac": round(fd_gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_node_step": 512},
-        "roofline": {"kernel": "fd_stage_kernel" if run_fd else "cs_step_kernel", "bound": "hbm",
-                     "achieved": round(fd_gbs if run_fd else cs_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round((fd_gbs if run_fd else cs_gbs) / HBM_PEAK_GBS, 4), "traffic": None},
     }
+    if run_fd:
+        # the FD stage dominates the step and is bound by vector ALU issue
+        flops_launch = nodes * (16 * sum(FD16_FLOPS_NODE_POP) / 3.0 + FD16_FLOPS_NODE)
+        tflops = flops_launch / (fd_stage_ms * 1e-3) / 1e12
+        line["roofline"] = {
+            "kernel": "fd_stage_kernel", "bound": "alu", "achieved": round(tflops, 2),
+            "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
+            "traffic": kernel_traffic("fd_stage_kernel", n),
+            "flops_per_launch": flops_launch,
+            "frac_of_published_fp32_peak": round(tflops / VALU_PEAK_PUBLISHED_TFLOPS, 4),
+            "hbm_frac_stagewise": round(fd_gbs / HBM_PEAK_GBS, 4)}
+    else:
+        line["roofline"] = {
+            "kernel": "cs_step_vec_kernel", "bound": "hbm", "achieved": round(cs_gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(cs_gbs / HBM_PEAK_GBS, 4), "traffic": kernel_traffic("cs_step_vec_kernel", n)}
     if args.copy_calibration:
         src = torch.empty(bytes_cs // 8, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
