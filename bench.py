@@ -233,30 +233,34 @@ def main():
     run_cs = args.only in (None, "cs")
     run_fd = args.only in (None, "fd")
 
-    def step():
-        if run_cs:
-            cs.step_sampled(1, every)
-        if run_fd:
-            fd.step_sampled(1, every)
+    # The two models advance in blocks of `every` steps: one sampled step
+    # (diagnostics fused) and every - 1 plain steps, which the library
+    # replays as captured HIP graphs.
+    def chunks(n):
+        return [every] * (n // every) + ([n % every] if n % every else [])
 
-    for _ in range(W):
-        step()
+    for c in chunks(W):
+        if run_cs:
+            cs.step_sampled(c, every)
+        if run_fd:
+            fd.step_sampled(c, every)
     torch.cuda.synchronize()
     cs.series_read()
     fd.series_read()
 
+    timed = chunks(K)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+           torch.cuda.Event(enable_timing=True)) for _ in timed]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for i in range(K):
+        for i, c in enumerate(timed):
             ev[i][0].record(stream)
             if run_cs:
-                cs.step_sampled(1, every)
+                cs.step_sampled(c, every)
             ev[i][1].record(stream)
             if run_fd:
-                fd.step_sampled(1, every)
+                fd.step_sampled(c, every)
             ev[i][2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

@@ -164,6 +164,18 @@ int lb_set_state(lb_sim *sim, const double *f);
 /* Number of steps taken since lb_init / lb_set_state. */
 long long lb_steps_done(const lb_sim *sim);
 
+/* Graph replay of plain steps (a performance setting; results are
+ * bitwise the same).  Runs of steps without sampling in lb_step and
+ * lb_step_sampled replay a HIP graph captured once with `steps` steps
+ * (rounded up to even for CS, whose two buffers then return to their start);
+ * the remainder of a run is launched step by step.  steps = -1 restores the
+ * default (CS 8, FD 4), 0 launches every step separately.  FP16 storage never
+ * replays graphs: its stochastic rounding draws new random bits every step.
+ * Captured graphs are dropped (and recaptured on demand) by lb_init,
+ * lb_set_state, lb_set_weno_eps and this call.  Returns LB_EINVAL for steps
+ * outside [-1, 4096]. */
+int lb_set_graph_steps(lb_sim *sim, int steps);
+
 /* Launch on a caller-owned HIP stream (hipStream_t passed as void*; NULL
  * means the library's own stream).  The caller keeps the stream alive. */
 int lb_set_stream(lb_sim *sim, void *hip_stream);

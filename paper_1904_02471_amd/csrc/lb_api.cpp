@@ -211,6 +211,73 @@ hipError_t step_once(lb_sim *s, bool with_diag)
     return e;
 }
 
+// ---------------------------------------------------------------------
+// Graph replay of plain steps.  The kernel arguments of a run of steps
+// without sampling repeat exactly (CS: after an even number of steps the
+// ping-pong pair is back at its start; FD: the buffers never move), so a
+// captured graph of G steps replays any run of G steps with one launch.
+// FP16 storage is excluded: its stochastic rounding draws fresh random bits
+// every step, which a replayed graph would repeat.
+int graph_len(const lb_sim *s)
+{
+    if (s->prec == P16) return 0;
+    int g = s->graph_steps < 0 ? (s->cs ? 8 : 4) : s->graph_steps;
+    if (s->cs && (g & 1)) ++g;
+    return g;
+}
+
+void drop_graphs(lb_sim *s)
+{
+    for (auto &g : s->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+template <typename T>
+hipError_t capture_steps(lb_sim *s, int G, hipGraphExec_t *out)
+{
+    hipError_t e = hipSuccess;
+    if (!s->cap_stream) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    const long long steps0 = s->steps;
+    const int cur0 = s->cur;
+    hipStream_t user = s->stream;
+    s->stream = s->cap_stream;
+    e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int i = 0; i < G && e == hipSuccess; ++i) e = step_once<T>(s, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    s->stream = user;
+    s->steps = steps0;
+    s->cur = cur0;
+    return e;
+}
+
+// n steps without sampling: whole graphs, then single launches.
+template <typename T>
+hipError_t plain_steps(lb_sim *s, long long n)
+{
+    hipError_t e = hipSuccess;
+    const int G = graph_len(s);
+    while (G > 0 && n >= G && e == hipSuccess) {
+        hipGraphExec_t &ge = s->graph[s->cs ? s->cur : 0];
+        if (!ge) e = capture_steps<T>(s, G, &ge);
+        if (e == hipSuccess) e = hipGraphLaunch(ge, s->stream);
+        if (e == hipSuccess) {
+            s->steps += G;  // CS: G is even, the current buffer is unchanged
+            n -= G;
+        }
+    }
+    for (; n > 0 && e == hipSuccess; --n) e = step_once<T>(s, false);
+    return e;
+}
+
 int diag_blocks_fused(const lb_sim *s) { return s->cs ? cs_diag_blocks(s->Nx, s->Ny) : fd_diag_blocks(s->Nx, s->Ny); }
 
 // Convert the device sums (sum drho, sum jx, sum jy, sum rho u^2/2, sum u.phi)
@@ -375,6 +442,8 @@ void lb_destroy(lb_sim *s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     free_buffers(s);
     if (s->d_partial) (void)hipFree(s->d_partial);
     if (s->d_out) (void)hipFree(s->d_out);
@@ -390,6 +459,7 @@ int lb_set_bc_x(lb_sim *s, double rho_left, double rho_right)
     if (!s || !(rho_left > 0) || !(rho_right > 0) || !std::isfinite(rho_left) || !std::isfinite(rho_right))
         return fail(LB_EINVAL);
     if (s->ready) return fail(LB_ESTATE);
+    drop_graphs(s);
     const bool relayout = s->cs && !s->fixed;
     s->fixed = true;
     s->rho_l = rho_left;
@@ -408,6 +478,8 @@ int lb_set_weno_eps(lb_sim *s, double eps)
     // the WENO weights use (eps + beta)^4, which must stay a normal number
     const double lo = s->prec == P64 ? 1e-75 : 1e-9, hi = s->prec == P64 ? 1e75 : 1e9;
     if (eps < lo || eps > hi) return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
     s->eps = eps;
     return LB_OK;
 }
@@ -473,6 +545,8 @@ int lb_init(lb_sim *s, const double *rho, const double *ux, const double *uy)
             return fail(LB_EINVAL);
         mean += rho[i];
     }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
     s->rho0 = mean / (double)n;
     s->cur = 0;
     int rc = ghosts_and(s);
@@ -508,6 +582,8 @@ int lb_set_state(lb_sim *s, const double *f)
         if (!std::isfinite(f[i])) return fail(LB_EINVAL);
         mass += f[i];
     }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
     s->rho0 = mass / (double)nodes;
     s->cur = 0;
     int rc = ghosts_and(s);
@@ -626,13 +702,20 @@ int lb_step(lb_sim *s, int nsteps)
 {
     if (!s || nsteps < 0) return fail(LB_EINVAL);
     if (!s->ready) return fail(LB_ESTATE);
-    for (int i = 0; i < nsteps; ++i) {
-        hipError_t e = with_type(s, [&](auto *tag) {
-            using T = std::remove_pointer_t<decltype(tag)>;
-            return step_once<T>(s, false);
-        });
-        if (e != hipSuccess) return fail(dev_status(e));
-    }
+    hipError_t e = with_type(s, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return plain_steps<T>(s, nsteps);
+    });
+    if (e != hipSuccess) return fail(dev_status(e));
+    return LB_OK;
+}
+
+int lb_set_graph_steps(lb_sim *s, int steps)
+{
+    if (!s || steps < -1 || steps > 4096) return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
+    s->graph_steps = steps;
     return LB_OK;
 }
 
@@ -686,14 +769,23 @@ static int sampled_steps(lb_sim *s, int nsteps, int every, long long base)
         if ((t - base) % every == 0) ++need;
     if ((long long)s->series_t.size() + need > s->series_cap) return LB_EBUSY;
     hipError_t e = hipSuccess;
-    for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
+    const long long end = s->steps + nsteps;
+    while (s->steps < end && e == hipSuccess) {
         const long long t = s->steps;
-        const bool sample = ((t - base) % every) == 0;
+        const long long phase = ((t - base) % every + every) % every;
+        if (phase != 0) {  // the run of plain steps up to the next sample
+            const long long run = std::min(end - t, (long long)every - phase);
+            e = with_type(s, [&](auto *tag) {
+                using T = std::remove_pointer_t<decltype(tag)>;
+                return plain_steps<T>(s, run);
+            });
+            continue;
+        }
         e = with_type(s, [&](auto *tag) {
             using T = std::remove_pointer_t<decltype(tag)>;
-            return step_once<T>(s, sample);
+            return step_once<T>(s, true);
         });
-        if (e == hipSuccess && sample) {
+        if (e == hipSuccess) {
             e = launch_diag_finalize(s->d_partial, diag_blocks_fused(s), s->d_series + kDiag * s->series_t.size(),
                                      s->stream);
             s->series_t.push_back(t);

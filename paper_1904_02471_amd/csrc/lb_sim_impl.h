@@ -46,6 +46,11 @@ struct lb_sim {
     int series_cap = 0;
     std::vector<long long> series_t;  // step index of each pending sample
     std::vector<char> series_fused;   // sums in the step kernel's velocity unit
+    // Runs of plain steps replay a captured graph of graph_len steps (CS: one
+    // per starting buffer; FD: [0]); dropped whenever the parameters change.
+    int graph_steps = -1;             // -1: the model's default, 0: no graphs
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;
 };
 
 namespace lbm {

@@ -1,0 +1,70 @@
+"""Graph replay of plain steps (lb_set_graph_steps): bitwise the same states
+and diagnostics as launching every step, over several replays with eager
+work and synchronisation between them, across lb_set_state (which drops the
+captured graphs) and for odd graph lengths."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1904_02471_amd import lb, workloads
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (lb.LB_CS_D2Q9, 64, 48, lb.LB_FP32),
+    (lb.LB_CS_D2Q9, 37, 20, lb.LB_FP64),    # scalar row form
+    (lb.LB_CS_D2Q9, 64, 16, lb.LB_FP16_SHIFTED),
+    (lb.LB_FD_D2Q16, 70, 40, lb.LB_FP32),
+    (lb.LB_FD_D2Q36, 33, 20, lb.LB_FP64),
+]
+
+
+def make(model, Nx, Ny, prec):
+    if model == lb.LB_CS_D2Q9:
+        return lb.Sim(model, Nx, Ny, 0.62, 1.0, 1.0, 2, precision=prec)
+    ds = 1.0 / Nx
+    vmax = lb.lb_model_info(model)[0].max()
+    dt = 0.5 * ds / vmax
+    return lb.Sim(model, Nx, Ny, 2 * dt, dt, ds, 4 if model == lb.LB_FD_D2Q36 else 3, precision=prec)
+
+
+@pytest.mark.parametrize("model,Nx,Ny,prec", CASES)
+def test_graph_replay_equals_step_by_step(model, Nx, Ny, prec):
+    print("case: graphs", model, Nx, Ny, prec, flush=True)
+    eager, graph = make(model, Nx, Ny, prec), make(model, Nx, Ny, prec)
+    eager.set_graph_steps(0)
+    f0 = workloads.random_distribution(eager.K, Nx, Ny, 5 + Nx, eager.w, spread=0.2)
+    rho, ux, uy = workloads.random_state(Nx, Ny, 9 + Ny, eager.cs)
+    for g in (eager, graph):
+        g.set_state(f0)
+        g.set_probe(*workloads.separable_pattern("tgv", Nx, Ny))
+        g.series_reserve(64)
+    # several replays, eager work (state reads) between them
+    for n in (3, 21, 8, 1, 16):
+        eager.step(n)
+        graph.step(n)
+        assert np.array_equal(eager.get_state(), graph.get_state()), n
+    # runs between samples
+    eager.step_sampled(37, 5)
+    graph.step_sampled(37, 5)
+    assert np.array_equal(eager.series_read(), graph.series_read())
+    assert np.array_equal(eager.get_state(), graph.get_state())
+    # a new state drops the graphs; an odd length is rounded up for CS
+    for g in (eager, graph):
+        g.init(rho, ux, uy)
+    graph.set_graph_steps(3)
+    for n in (7, 12, 5):
+        eager.step(n)
+        graph.step(n)
+        assert np.array_equal(eager.get_state(), graph.get_state()), ("after init", n)
+    assert eager.steps_done() == graph.steps_done() == 24
+
+
+def test_graph_steps_argument_range():
+    g = make(lb.LB_CS_D2Q9, 16, 8, lb.LB_FP32)
+    with pytest.raises(lb.LBError):
+        g.set_graph_steps(-2)
+    with pytest.raises(lb.LBError):
+        g.set_graph_steps(5000)
+    g.set_graph_steps(-1)
