@@ -230,6 +230,8 @@ def main():
     cap = (K + W) // every + 2
     cs.series_reserve(cap)
     fd.series_reserve(cap)
+    # launch shapes of the plain steps chosen by the library's autotuner
+    tuned = {"cs_threads": cs.autotune(10)[0], "fd_tile_rows": fd.autotune(5)[1]}
     run_cs = args.only in (None, "cs")
     run_fd = args.only in (None, "fd")
 
@@ -298,6 +300,7 @@ def main():
                         "(shifted), FP64 diagnostics fused every %d steps; one update = one node advanced by "
                         "one CS step and one FD step" % (n, n, prm["tau_fd"], prm["dt_fd"], every),
             "grid": [n, n],
+            "launch_shapes": tuned,
             "models": ["cs_d2q9" if run_cs else None, "fd_d2q16" if run_fd else None],
         },
         "cs_d2q9": {"ms_per_step": round(cs_ms, 5),

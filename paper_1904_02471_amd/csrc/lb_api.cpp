@@ -9,6 +9,7 @@
 #include <limits>
 #include <new>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "lb.h"
@@ -199,13 +200,13 @@ hipError_t step_once(lb_sim *s, bool with_diag)
     const DiagArgs<CT> *dp = with_diag ? &d : nullptr;
     hipError_t e;
     if (s->cs) {
-        e = launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, dp, s->stream);
+        e = launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, dp, s->stream, s->cs_threads);
         s->cur ^= 1;
     } else {
         T *g = bufp<T>(s, 0), *a = bufp<T>(s, 1), *b = bufp<T>(s, 2);
-        e = launch_fd_stage<T>(g, nullptr, a, 1, p, dp, s->stream);
-        if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream);
-        if (e == hipSuccess) e = launch_fd_stage<T>(b, g, g, 3, p, nullptr, s->stream);
+        e = launch_fd_stage<T>(g, nullptr, a, 1, p, dp, s->stream, dp ? 8 : s->fd_rows);
+        if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, s->fd_rows);
+        if (e == hipSuccess) e = launch_fd_stage<T>(b, g, g, 3, p, nullptr, s->stream, s->fd_rows);
     }
     if (e == hipSuccess) ++s->steps;
     return e;
@@ -275,6 +276,37 @@ hipError_t plain_steps(lb_sim *s, long long n)
         }
     }
     for (; n > 0 && e == hipSuccess; --n) e = step_once<T>(s, false);
+    return e;
+}
+
+// ---------------------------------------------------------------------
+// Autotuning of the plain-step launch shapes.  Candidates are timed on the
+// handle's own buffers with launches that leave the state untouched: a CS
+// step from the current buffer into the other one (which the next step
+// overwrites), FD stages 1 and 2 into the stage buffers A and B.
+template <typename T>
+hipError_t time_candidate(lb_sim *s, int cs_threads, int fd_rows, int reps, float *ms)
+{
+    using CT = typename Arith<T>::type;
+    const Params<CT> p = make_params<CT>(s);
+    auto launch = [&]() -> hipError_t {
+        if (s->cs) return launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, nullptr, s->stream, cs_threads);
+        T *g = bufp<T>(s, 0), *a = bufp<T>(s, 1), *b = bufp<T>(s, 2);
+        hipError_t e = launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, fd_rows);
+        if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, fd_rows);
+        return e;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     return e;
 }
 
@@ -707,6 +739,59 @@ int lb_step(lb_sim *s, int nsteps)
         return plain_steps<T>(s, nsteps);
     });
     if (e != hipSuccess) return fail(dev_status(e));
+    return LB_OK;
+}
+
+int lb_autotune(lb_sim *s, int reps)
+{
+    if (!s || reps < 1 || reps > 1000) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    std::vector<std::pair<int, int>> cand;  // (cs_threads, fd_rows)
+    if (s->cs) {
+        const int w = s->prec == P64 ? 2 : 4;  // values per vector chunk
+        if (!s->fixed && s->Nx % w == 0)
+            for (int t : {0, 256, 512, 1024}) cand.push_back({t, 8});
+    } else {
+        for (int r : {8, 4}) cand.push_back({0, r});
+    }
+    if (cand.size() < 2) return LB_OK;  // nothing to choose
+    float best = 0.0f;
+    std::pair<int, int> pick = cand[0];
+    for (const auto &c : cand) {
+        float ms = 0.0f;
+        hipError_t e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return time_candidate<T>(s, c.first, c.second, reps, &ms);
+        });
+        if (e != hipSuccess) return fail(dev_status(e));
+        if (&c == &cand[0] || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    drop_graphs(s);
+    s->cs_threads = pick.first;
+    s->fd_rows = pick.second;
+    return LB_OK;
+}
+
+int lb_set_tuning(lb_sim *s, int cs_threads, int fd_rows)
+{
+    if (!s || cs_threads < 0 || cs_threads > 1024 || cs_threads % 64 || (fd_rows != 4 && fd_rows != 8))
+        return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
+    s->cs_threads = cs_threads;
+    s->fd_rows = fd_rows;
+    return LB_OK;
+}
+
+int lb_get_tuning(const lb_sim *s, int *cs_threads, int *fd_rows)
+{
+    if (!s || !cs_threads || !fd_rows) return fail(LB_EINVAL);
+    *cs_threads = s->cs_threads;
+    *fd_rows = s->fd_rows;
     return LB_OK;
 }
 

@@ -24,11 +24,12 @@ __global__ __launch_bounds__(1024) void cs_step_vec_kernel(const T *__restrict__
 
 template <typename T, bool FIXED>
 hipError_t launch_cs_t(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
-                       const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s)
+                       const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int threads)
 {
     dim3 grid(p.Ny), block(kCsThreads);
     if (!FIXED && cs_vec_ok<T>(p)) {
-        const dim3 vblock(cs_vec_threads<T>(p.Nx));
+        // sampled steps keep the canonical size (their diagnostics sum per thread)
+        const dim3 vblock(diag || threads <= 0 ? cs_vec_threads<T>(p.Nx) : threads);
         if (diag) {
             hipLaunchKernelGGL((cs_step_vec_kernel<T, true>), grid, vblock, 0, s, src, dst, p, *diag);
         } else {
@@ -52,17 +53,17 @@ int cs_diag_blocks(int /*Nx*/, int Ny) { return Ny; }
 
 template <typename T>
 hipError_t launch_cs_step(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
-                          const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s)
+                          const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int threads)
 {
-    if (p.fixed_x) return launch_cs_t<T, true>(src, dst, p, diag, s);
-    return launch_cs_t<T, false>(src, dst, p, diag, s);
+    if (p.fixed_x) return launch_cs_t<T, true>(src, dst, p, diag, s, threads);
+    return launch_cs_t<T, false>(src, dst, p, diag, s, threads);
 }
 
 template hipError_t launch_cs_step<float>(const float *, float *, const Params<float> &, const DiagArgs<float> *,
-                                          hipStream_t);
+                                          hipStream_t, int);
 template hipError_t launch_cs_step<__half>(const __half *, __half *, const Params<float> &,
-                                           const DiagArgs<float> *, hipStream_t);
+                                           const DiagArgs<float> *, hipStream_t, int);
 template hipError_t launch_cs_step<double>(const double *, double *, const Params<double> &,
-                                           const DiagArgs<double> *, hipStream_t);
+                                           const DiagArgs<double> *, hipStream_t, int);
 
 }  // namespace lbm

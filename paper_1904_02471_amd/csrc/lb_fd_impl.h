@@ -44,17 +44,29 @@
 namespace lbm {
 
 
-constexpr int kTX = 64, kTY = 32, kRows = 8;
+constexpr int kTX = 64;
 constexpr int kFdThreads = 256;
 constexpr int kHalo = 3;
 constexpr int kLX = kTX + 2 * kHalo;  // 70
-constexpr int kLY = kTY + 2 * kHalo;  // 38
-constexpr int kTileElems = kLX * kLY;
-constexpr int kLoadsPerThread = (kTileElems + kFdThreads - 1) / kFdThreads;
 constexpr int kXFaceStride = kTX + 1;  // x-faces per tile row
-constexpr int kSeg = 8;                // x-faces per marching segment
-static_assert(kTY * (kTX / kSeg) == kFdThreads, "one x-face segment per thread");
-static_assert(kTY <= 64, "the column-0 faces are computed by one wave");
+// Canonical tile height (rows per thread 8: 64 x 32 tiles).  Sampled stages,
+// whose diagnostics partials are indexed by tile, and the batched launches
+// always use it; plain stages may use a tuned height.
+constexpr int kFdRows = 8;
+
+// Tile geometry for ROWS rows per thread: 64 x (4 ROWS) tiles, the tile with
+// its halo staged in LDS, x-faces marched in segments of kSeg per thread.
+template <int ROWS>
+struct FdGeom {
+    static constexpr int kRows = ROWS;
+    static constexpr int kTY = 4 * ROWS;
+    static constexpr int kLY = kTY + 2 * kHalo;
+    static constexpr int kTileElems = kLX * kLY;
+    static constexpr int kLoadsPerThread = (kTileElems + kFdThreads - 1) / kFdThreads;
+    static constexpr int kSeg = kTX * kTY / kFdThreads;
+    static_assert(kTY * (kTX / kSeg) == kFdThreads, "one x-face segment per thread");
+    static_assert(kTY <= 64, "the column-0 faces are computed by one wave");
+};
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
@@ -109,10 +121,12 @@ __device__ __forceinline__ int fd_wrap(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-// One 64 x 32 tile (bx, by) of a Runge-Kutta stage, by a 256-thread
+// One 64 x (4 ROWS) tile (bx, by) of a Runge-Kutta stage, by a 256-thread
 // workgroup; with `diag` the diagnostics of the tile's input state go to
-// partial[diag_block].
-template <typename T, int N, bool FIXED, bool WITH_GN>
+// partial[diag_block].  Every face and node is evaluated by the same
+// sequence of operations for any ROWS, so the stage output does not depend
+// on the tile height.
+template <typename T, int N, bool FIXED, bool WITH_GN, int ROWS = kFdRows>
 __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T *gn, T *out,
                                               const typename Arith<T>::type cb,
                                               const Params<typename Arith<T>::type> &p,
@@ -120,6 +134,10 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                                               int diag_block, bool diag)
 {
     using CT = typename Arith<T>::type;
+    using G = FdGeom<ROWS>;
+    constexpr int kRows = G::kRows, kTY = G::kTY, kLY = G::kLY, kTileElems = G::kTileElems;
+    constexpr int kLoadsPerThread = G::kLoadsPerThread, kSeg = G::kSeg;
+    (void)kLY;
     __shared__ CT tile[2][kTileElems];
     __shared__ CT xface[kTY * kXFaceStride];
     // FP32 storage: tiles and the Runge-Kutta base values are copied from

@@ -139,12 +139,17 @@ template <> __device__ __forceinline__ double ld<double>(const double *p) { retu
 
 // Hot-path launchers (lb_cs.hip, lb_fd.hip).  `diag` non-NULL fuses the
 // diagnostics of the step's input state.
+// `threads`: workgroup size of plain steps in the vector row form (0: the
+// default, one chunk per thread); sampled steps always use the default.
 template <typename T>
 hipError_t launch_cs_step(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
-                          const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s);
+                          const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int threads = 0);
+// `rows`: rows per thread of the stage tiles (8: 64 x 32, the canonical
+// tiles; 4: 64 x 16, a tuning choice for stages without diagnostics); the
+// output does not depend on it.
 template <typename T>
 hipError_t launch_fd_stage(const T *src, const T *gn, T *out, int stage, const Params<typename Arith<T>::type> &p,
-                           const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s);
+                           const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int rows = 8);
 int cs_diag_blocks(int Nx, int Ny);
 int fd_diag_blocks(int Nx, int Ny);
 

@@ -21,7 +21,8 @@ Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_F
 EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
            "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
-           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_stream", "lb_synchronize",
+           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_autotune", "lb_set_tuning",
+           "lb_get_tuning", "lb_set_stream", "lb_synchronize",
            "lb_device_bytes",
            "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
            "lb_server_stats", "lb_server_destroy"]
@@ -62,6 +63,9 @@ def _load():
         "lb_set_state": (ctypes.c_int, [_vp, _dp]),
         "lb_steps_done": (ctypes.c_longlong, [_vp]),
         "lb_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+        "lb_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "lb_set_stream": (ctypes.c_int, [_vp, _vp]),
         "lb_synchronize": (ctypes.c_int, [_vp]),
         "lb_device_bytes": (ctypes.c_size_t, [_vp]),
@@ -205,6 +209,19 @@ class Sim:
         """Steps per replayed HIP graph for runs of plain steps (-1: default, 0: off)."""
         _check(_lib.lb_set_graph_steps(self._h, int(steps)), "lb_set_graph_steps")
 
+    def autotune(self, reps=20):
+        """Time the plain-step launch shapes on this simulation and keep the fastest."""
+        _check(_lib.lb_autotune(self._h, int(reps)), "lb_autotune")
+        return self.tuning()
+
+    def set_tuning(self, cs_threads, fd_rows):
+        _check(_lib.lb_set_tuning(self._h, int(cs_threads), int(fd_rows)), "lb_set_tuning")
+
+    def tuning(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.lb_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)), "lb_get_tuning")
+        return a.value, b.value
+
     def set_stream(self, stream_handle):
         """stream_handle: an integer hipStream_t (e.g. torch.cuda.Stream().cuda_stream) or 0/None."""
         _check(_lib.lb_set_stream(self._h, ctypes.c_void_p(int(stream_handle or 0))), "lb_set_stream")
@@ -283,6 +300,18 @@ def lb_steps_done(sim):
 
 def lb_set_graph_steps(sim, steps):
     sim.set_graph_steps(steps)
+
+
+def lb_autotune(sim, reps=20):
+    return sim.autotune(reps)
+
+
+def lb_set_tuning(sim, cs_threads, fd_rows):
+    sim.set_tuning(cs_threads, fd_rows)
+
+
+def lb_get_tuning(sim):
+    return sim.tuning()
 
 
 def lb_set_stream(sim, stream_handle):

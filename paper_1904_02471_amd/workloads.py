@@ -59,7 +59,7 @@ def separable_pattern(kind, Nx, Ny):
     if kind == "shear_y":
         return np.ones(Nx), np.sin(ky * y), np.zeros(Nx), np.zeros(Ny)
     if kind == "shear_x":
-        return np.zeros(Nx), np.zeros(Ny), np.ones(Nx), np.sin(kx * x)
+        return np.zeros(Nx), np.zeros(Ny), np.sin(kx * x), np.ones(Ny)
     if kind == "tgv":
         return np.sin(kx * x), np.cos(ky * y), -np.cos(kx * x), np.sin(ky * y)
     raise ValueError(kind)

@@ -101,3 +101,18 @@ def test_units_match_printed_values(golden):
     assert units.tau_fd_from_std(0.6, 512) == pytest.approx(1.12764e-4, rel=1e-5)
     assert units.tau_std_from_lu(units.tau_lu_from_fd(units.tau_fd_from_std(0.8, 64), 64)) == pytest.approx(0.8)
     assert units.fd_time_step(5e-4, 1 / 2048, 3.324257, 0.5) == pytest.approx(7.3442e-5, rel=1e-4)
+
+
+@pytest.mark.parametrize("kind,Nx,Ny", [("shear_y", 12, 7), ("shear_x", 12, 7), ("shear_x", 9, 1), ("tgv", 10, 6)])
+def test_separable_patterns_match_the_initial_fields(kind, Nx, Ny):
+    """The probe patterns of the diagnostics are the initial velocity
+    patterns, as products of 1-D factors."""
+    from paper_1904_02471_amd import workloads
+    ax, ay, bx, by = workloads.separable_pattern(kind, Nx, Ny)
+    assert ax.shape == bx.shape == (Nx,) and ay.shape == by.shape == (Ny,)
+    if kind == "tgv":
+        _, _, _, (px, py) = workloads.taylor_green(Nx, Ny, 1.0, 1.0)
+    else:
+        _, _, _, (px, py) = workloads.shear_wave(Nx, Ny, 1.0, kind[-1])
+    np.testing.assert_allclose(np.outer(ay, ax), px, atol=1e-15)
+    np.testing.assert_allclose(np.outer(by, bx), py, atol=1e-15)

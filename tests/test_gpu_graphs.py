@@ -68,3 +68,49 @@ def test_graph_steps_argument_range():
     with pytest.raises(lb.LBError):
         g.set_graph_steps(5000)
     g.set_graph_steps(-1)
+
+
+@pytest.mark.parametrize("model,Nx,Ny,prec,shapes", [
+    (lb.LB_CS_D2Q9, 256, 24, lb.LB_FP32, [(64, 8), (256, 8), (512, 8), (1024, 8)]),
+    (lb.LB_CS_D2Q9, 100, 10, lb.LB_FP64, [(128, 8)]),
+    (lb.LB_FD_D2Q16, 70, 40, lb.LB_FP32, [(0, 4)]),
+    (lb.LB_FD_D2Q36, 65, 33, lb.LB_FP64, [(0, 4)]),
+    (lb.LB_FD_D2Q16, 64, 48, lb.LB_FP16_SHIFTED, [(0, 4)]),
+])
+def test_launch_shapes_do_not_change_results(model, Nx, Ny, prec, shapes):
+    """Every tuned launch shape (CS workgroup size, FD tile height) gives
+    bitwise the same states and diagnostics; autotuning leaves the state
+    untouched and picks one of the candidates."""
+    print("case: tuning", model, Nx, Ny, prec, flush=True)
+    f0 = None
+    ref = None
+    for shape in [None] + shapes:
+        g = make(model, Nx, Ny, prec)
+        if f0 is None:
+            f0 = workloads.random_distribution(g.K, Nx, Ny, 3 + Nx, g.w, spread=0.2)
+        g.set_state(f0)
+        g.set_probe(*workloads.separable_pattern("tgv", Nx, Ny))
+        g.series_reserve(16)
+        if shape is not None:
+            g.set_tuning(*shape)
+            assert g.tuning() == shape
+        g.step(9)
+        g.step_sampled(23, 4)
+        out = (g.get_state(), g.series_read())
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]), shape
+            assert np.array_equal(out[1], ref[1]), shape
+    g = make(model, Nx, Ny, prec)
+    g.set_state(f0)
+    g.set_probe(*workloads.separable_pattern("tgv", Nx, Ny))
+    g.series_reserve(16)
+    before = g.get_state()
+    cs_threads, fd_rows = g.autotune(3)
+    assert np.array_equal(g.get_state(), before)
+    assert fd_rows in (4, 8) and cs_threads in (0, 256, 512, 1024)
+    g.step(9)
+    g.step_sampled(23, 4)
+    assert np.array_equal(g.get_state(), ref[0])
+    assert np.array_equal(g.series_read(), ref[1])
