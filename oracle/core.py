@@ -39,6 +39,7 @@ def _load():
     lib.orc_sound_speed.restype = ctypes.c_double
     lib.orc_velocities.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
     lib.orc_set_weno_eps.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    lib.orc_set_time_scheme.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc_set_bc_x.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
     lib.orc_equilibrium.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
     lib.orc_init.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
@@ -124,6 +125,11 @@ class OracleSim:
 
     def set_weno_eps(self, eps):
         self._lib.orc_set_weno_eps(self._h, eps)
+
+    def set_time_scheme(self, scheme):
+        """FD only: 0 third-order TVD Runge-Kutta, 1 IMEX-SSP2(2,2,2) (advection
+        explicit, BGK relaxation implicit)."""
+        self._lib.orc_set_time_scheme(self._h, int(scheme))
 
     def set_bc_x(self, rho_left, rho_right):
         self._lib.orc_set_bc_x(self._h, rho_left, rho_right)

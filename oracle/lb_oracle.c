@@ -36,6 +36,7 @@ typedef struct orc_sim {
     int bc_x_fixed;
     double rho_left, rho_right;
     double weno_eps;
+    int time_scheme; /* FD: 0 third-order TVD Runge-Kutta, 1 IMEX-SSP2(2,2,2) */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -413,11 +414,98 @@ static void fd_step_once(orc_sim *s)
     for (long i = 0; i < n; ++i) s->f[i] = s->f[i] / 3.0 + 2.0 / 3.0 * (f2[i] + dt * L[i]);
 }
 
+/* Implicit-explicit time stepping.
+ * READING: Section 4.1 names implicit-explicit (IMEX) schemes as the way to
+ * lift the restriction dt < tau_FD, without giving one.  We take the
+ * second-order IMEX-SSP2(2,2,2) Runge-Kutta scheme of Pareschi & Russo
+ * (J. Sci. Comput. 25, 2005): the advection A(f) explicit with the SSP
+ * (Heun) tableau, the BGK relaxation R(f) = -(f - f_eq(f)) / tau implicit
+ * with the L-stable tableau [[g, 0], [1 - 2g, g]], g = 1 - 1/sqrt(2), both
+ * with weights (1/2, 1/2):
+ *   f1 = f + g dt R(f1)
+ *   f2 = f + dt A(f1) + (1 - 2g) dt R(f1) + g dt R(f2)
+ *   f' = f + dt/2 [A(f1) + A(f2)] + dt/2 [R(f1) + R(f2)]
+ * R leaves rho and rho u unchanged, so f_eq(f_i) is the equilibrium of the
+ * explicit part h of its stage, and each implicit stage has the closed form
+ *   f_i = (h + (g dt / tau) f_eq(h)) / (1 + g dt / tau). */
+
+/* out = advection term -v . grad f (WENO-5 faces, as in fd_rhs). */
+static void fd_advection(const orc_sim *s, const double *f, double *out)
+{
+    int Nx = s->Nx, Ny = s->Ny, K = s->K;
+    long plane = (long)Nx * Ny;
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            long node = (long)y * Nx + x;
+            for (int k = 0; k < K; ++k) {
+                double adv = 0.0;
+                if (s->vx[k] != 0.0) {
+                    double fr = fd_interface(s, f, k, x, y, 1, 0, s->vx[k]);
+                    double fl = fd_interface(s, f, k, x - 1, y, 1, 0, s->vx[k]);
+                    adv += s->vx[k] * (fr - fl) / s->ds;
+                }
+                if (s->vy[k] != 0.0) {
+                    double gr = fd_interface(s, f, k, x, y, 0, 1, s->vy[k]);
+                    double gl = fd_interface(s, f, k, x, y - 1, 0, 1, s->vy[k]);
+                    adv += s->vy[k] * (gr - gl) / s->ds;
+                }
+                out[k * plane + node] = -adv;
+            }
+        }
+}
+
+/* out = relaxation term -(f - f_eq(f)) / tau. */
+static void fd_relaxation(const orc_sim *s, const double *f, double *out)
+{
+    long plane = (long)s->Nx * s->Ny;
+    for (long node = 0; node < plane; ++node) {
+        double rho, ux, uy;
+        moments_node(s, f, node, plane, &rho, &ux, &uy);
+        for (int k = 0; k < s->K; ++k)
+            out[k * plane + node] = -(f[k * plane + node] - feq_one(s, k, rho, ux, uy)) / s->tau;
+    }
+}
+
+/* out = the solution f_i of f_i = h + a tau R(f_i), a = g dt / tau. */
+static void fd_implicit_relax(const orc_sim *s, const double *h, double a, double *out)
+{
+    long plane = (long)s->Nx * s->Ny;
+    for (long node = 0; node < plane; ++node) {
+        double rho, ux, uy;
+        moments_node(s, h, node, plane, &rho, &ux, &uy);
+        for (int k = 0; k < s->K; ++k)
+            out[k * plane + node] = (h[k * plane + node] + a * feq_one(s, k, rho, ux, uy)) / (1.0 + a);
+    }
+}
+
+static void fd_imex_step_once(orc_sim *s)
+{
+    long n = (long)s->K * s->Nx * s->Ny;
+    double *f1 = s->work[0], *f2 = s->work[1], *A1 = s->work[2], *R1 = s->work[3];
+    double dt = s->dt, g = 1.0 - 1.0 / sqrt(2.0), a = g * dt / s->tau;
+    fd_implicit_relax(s, s->f, a, f1);
+    fd_advection(s, f1, A1);
+    fd_relaxation(s, f1, R1);
+    double *h = (double *)malloc(sizeof(double) * n);
+    for (long i = 0; i < n; ++i) h[i] = s->f[i] + dt * A1[i] + (1.0 - 2.0 * g) * dt * R1[i];
+    fd_implicit_relax(s, h, a, f2);
+    /* reuse h for A(f2) and then R(f2) terms */
+    fd_advection(s, f2, h);
+    for (long i = 0; i < n; ++i) s->f[i] += 0.5 * dt * (A1[i] + h[i]) + 0.5 * dt * R1[i];
+    fd_relaxation(s, f2, h);
+    for (long i = 0; i < n; ++i) s->f[i] += 0.5 * dt * h[i];
+    free(h);
+}
+
+void orc_set_time_scheme(orc_sim *s, int scheme) { s->time_scheme = scheme; }
+
 void orc_step(orc_sim *s, int nsteps)
 {
     for (int i = 0; i < nsteps; ++i) {
         if (s->model == ORC_CS_D2Q9)
             cs_step_once(s);
+        else if (s->time_scheme == 1)
+            fd_imex_step_once(s);
         else
             fd_step_once(s);
     }
