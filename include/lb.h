@@ -61,6 +61,21 @@ enum lb_precision {
 };
 #define LB_PRECISION_MASK (3 << 8)
 
+/* Time integration of the FD models (bit 10, or-ed into the model like the
+ * precision).  Default: the third-order TVD Runge-Kutta scheme with the BGK
+ * collision explicit in every stage (Section 2), which needs dt <= tau
+ * (Section 4.1, LB_ESTIFF otherwise).  LB_IMEX: an implicit-explicit scheme,
+ * which Section 4.1 names for lifting that bound without specifying one; the
+ * library takes IMEX-SSP2(2,2,2) (Pareschi & Russo 2005): advection explicit
+ * (SSP Heun tableau), relaxation implicit (L-stable tableau, solved in closed
+ * form because the collision keeps rho and rho u), second order, any dt/tau;
+ * the CFL bound still applies.  Four launches per step (two stencil stages,
+ * two pointwise relaxation stages), three state buffers.  The stencil stage
+ * re-evaluates the relaxation of the stored first stage explicitly, so its
+ * storage rounding is amplified by dt/tau (visible with FP16 storage at large
+ * dt/tau).  CS models reject it (LB_EINVAL). */
+#define LB_IMEX (1 << 10)
+
 enum lb_status {
     LB_OK = 0,
     LB_EINVAL = -1,  /* bad model, size, order, pointer or argument */

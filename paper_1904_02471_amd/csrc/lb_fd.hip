@@ -1,5 +1,7 @@
 // lb_fd.hip -- finite-difference Gauss-Hermite stage kernels for gfx950, one
 // simulation per launch (device code in lb_fd_impl.h).
+#include <cmath>
+
 #include "lb_fd_impl.h"
 
 namespace lbm {
@@ -20,6 +22,108 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
     const int tile = x * q + (x < r ? x : r) + b / 8;
     const int tiles_x = (p.Nx + kTX - 1) / kTX;
     fd_stage_tile<T, N, FIXED, WITH_GN, ROWS>(src, gn, out, cb, p, d, tile % tiles_x, tile / tiles_x, tile, DIAG);
+}
+
+// ---------------------------------------------------------------------
+// Implicit-explicit stepping (IMEX-SSP2(2,2,2)): the two pointwise stages.
+// An implicit relaxation stage solves f_i = h + a tau R(f_i), a = g dt / tau;
+// R keeps rho and rho u, so f_eq(f_i) = f_eq(h) and
+//   f_i = (h + a f_eq(h)) / (1 + a).
+// Moments and equilibrium are the stage kernel's (fd_node_correct, fd_geq).
+
+template <typename CT, int N>
+struct NodeEq {
+    CT drho, ux, uy, dlt;
+};
+
+// Moments of h at node offset o, h_k = hk(k) (a callable), with the same
+// summation order as the stage kernel's pre-pass.
+template <typename CT, int N, typename H>
+__device__ __forceinline__ NodeEq<CT, N> node_eq(const Params<CT> &p, H hk)
+{
+    CT drho = CT(0), jx = CT(0), jy = CT(0);
+    for (int k = 0; k < p.K; ++k) {
+        const CT g = hk(k);
+        drho += g;
+        jx = fmaT(g, p.vx[k], jx);
+        jy = fmaT(g, p.vy[k], jy);
+    }
+    NodeEq<CT, N> q;
+    const CT inv = CT(1) / (p.rho0 + drho);
+    q.drho = drho;
+    q.ux = jx * inv;
+    q.uy = jy * inv;
+    fd_node_correct<CT, N>(p, drho, jx, jy, q.ux, q.uy, q.dlt);
+    return q;
+}
+
+template <typename CT, int N>
+__device__ __forceinline__ CT node_geq(const Params<CT> &p, const NodeEq<CT, N> &q, int k)
+{
+    CT hx[N + 1], hy[N + 1];
+    hx[0] = hy[0] = CT(1);
+#pragma unroll
+    for (int n = 1; n <= N; ++n) {
+        hx[n] = p.hc[p.ki[k]][n];
+        hy[n] = p.hc[p.kj[k]][n];
+    }
+    return fd_geq<CT, N>(p.w[k], hx, hy, p.rho0, q.drho, q.ux, q.uy, q.dlt);
+}
+
+// First stage: out = relaxed g (one thread per node).
+template <typename T, int N>
+__global__ __launch_bounds__(256) void fd_imex_relax_kernel(const T *__restrict__ g, T *__restrict__ out,
+                                                            const Params<typename Arith<T>::type> p,
+                                                            typename Arith<T>::type a,
+                                                            typename Arith<T>::type inv1pa)
+{
+    using CT = typename Arith<T>::type;
+    const long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (node >= (long long)p.Nx * p.Ny) return;
+    const long long o = (node / p.Nx) * p.pitch + p.xoff + node % p.Nx;
+    const long long P = p.plane;
+    const NodeEq<CT, N> q = node_eq<CT, N>(p, [&](int k) { return ld(g + k * P + o); });
+    uint32_t rb = mix32((uint32_t)node, p.salt);
+    for (int k = 0; k < p.K; ++k) {
+        const CT h = ld(g + k * P + o);
+        rb = xorshift32(rb);
+        store_state(out + k * P + o, fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa, rb);
+    }
+}
+
+// Second stage, from y = f1 + dt L(f1) (in yb), f = g^n (in g) and f1 (in
+// f1b): the explicit part h = f + dt A(f1) + (1 - 2g) dt R(f1) is
+// y + 3 (f - f1) (as g dt R(f1) = f1 - f); writes f2 = relax(h) over yb and
+// b = 2 f1 + h - f - f2 over f1b, so that the last stage
+// f' = b + (f2 + dt L(f2) - b) / 2 equals f + dt/2 [L(f1) + L(f2)].
+template <typename T, int N>
+__global__ __launch_bounds__(256) void fd_imex_mid_kernel(T *__restrict__ yb, const T *__restrict__ g,
+                                                          T *__restrict__ f1b,
+                                                          const Params<typename Arith<T>::type> p,
+                                                          typename Arith<T>::type a,
+                                                          typename Arith<T>::type inv1pa)
+{
+    using CT = typename Arith<T>::type;
+    const long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (node >= (long long)p.Nx * p.Ny) return;
+    const long long o = (node / p.Nx) * p.pitch + p.xoff + node % p.Nx;
+    const long long P = p.plane;
+    auto hk = [&](int k) {
+        const CT f1 = ld(f1b + k * P + o);
+        return fmaT(CT(3), ld(g + k * P + o) - f1, ld(yb + k * P + o));
+    };
+    const NodeEq<CT, N> q = node_eq<CT, N>(p, hk);
+    uint32_t rb = mix32((uint32_t)node, p.salt);
+    for (int k = 0; k < p.K; ++k) {
+        const CT f1 = ld(f1b + k * P + o), f = ld(g + k * P + o);
+        const CT h = fmaT(CT(3), f - f1, ld(yb + k * P + o));
+        const CT f2 = fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa;
+        const CT b = fmaT(CT(2), f1, h - f) - f2;
+        rb = xorshift32(rb);
+        store_state(yb + k * P + o, f2, rb);
+        rb = xorshift32(rb);
+        store_state(f1b + k * P + o, b, rb);
+    }
 }
 
 template <typename T, int N, bool FIXED, int ROWS>
@@ -44,7 +148,8 @@ hipError_t launch_fd_rows(const T *src, const T *gn, T *out, int stage, const Pa
                                out, CT(1), ps, none);
         }
     } else {
-        const CT cb = (stage == 2) ? CT(0.25) : CT(2) / CT(3);
+        // stages 2 and 3 of RK-3; 4: the last IMEX stage
+        const CT cb = (stage == 2) ? CT(0.25) : (stage == 3 ? CT(2) / CT(3) : CT(0.5));
         hipLaunchKernelGGL((fd_stage_kernel<T, N, FIXED, false, true, ROWS>), grid, block, 0, s, src, gn, out, cb,
                            ps, none);
     }
@@ -73,7 +178,46 @@ hipError_t launch_fd_b(const T *src, const T *gn, T *out, int stage, const Param
     }
 }
 
+template <typename T, int N>
+hipError_t launch_imex_n(int which, T *a_buf, const T *g, T *b_buf, const Params<typename Arith<T>::type> &p,
+                         double dt_over_tau, hipStream_t s)
+{
+    using CT = typename Arith<T>::type;
+    const double gam = 1.0 - 1.0 / std::sqrt(2.0);
+    const CT a = (CT)(gam * dt_over_tau), inv1pa = (CT)(1.0 / (1.0 + gam * dt_over_tau));
+    const long long nodes = (long long)p.Nx * p.Ny;
+    const dim3 grid((unsigned)((nodes + 255) / 256)), block(256);
+    Params<CT> ps = p;
+    ps.salt = mix_host(p.salt * 3u + 5u + (unsigned)which);
+    if (which == 0)
+        hipLaunchKernelGGL((fd_imex_relax_kernel<T, N>), grid, block, 0, s, g, a_buf, ps, a, inv1pa);
+    else
+        hipLaunchKernelGGL((fd_imex_mid_kernel<T, N>), grid, block, 0, s, b_buf, g, a_buf, ps, a, inv1pa);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_fd_imex(int which, T *a_buf, const T *g, T *b_buf, const Params<typename Arith<T>::type> &p,
+                          double dt_over_tau, hipStream_t s)
+{
+    switch (p.N) {
+    case 1: return launch_imex_n<T, 1>(which, a_buf, g, b_buf, p, dt_over_tau, s);
+    case 2: return launch_imex_n<T, 2>(which, a_buf, g, b_buf, p, dt_over_tau, s);
+    case 3: return launch_imex_n<T, 3>(which, a_buf, g, b_buf, p, dt_over_tau, s);
+    case 4: return launch_imex_n<T, 4>(which, a_buf, g, b_buf, p, dt_over_tau, s);
+    case 5: return launch_imex_n<T, 5>(which, a_buf, g, b_buf, p, dt_over_tau, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_fd_imex<float>(int, float *, const float *, float *, const Params<float> &, double,
+                                          hipStream_t);
+template hipError_t launch_fd_imex<__half>(int, __half *, const __half *, __half *, const Params<float> &, double,
+                                           hipStream_t);
+template hipError_t launch_fd_imex<double>(int, double *, const double *, double *, const Params<double> &, double,
+                                           hipStream_t);
 
 int fd_diag_blocks(int Nx, int Ny)
 {

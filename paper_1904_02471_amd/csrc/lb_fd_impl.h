@@ -121,6 +121,96 @@ __device__ __forceinline__ int fd_wrap(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// Moment-exact equilibrium, per node.  The rounded tables give the
+// equilibrium mass and momentum defects of relative size ~1e-8 (polynomials
+// in u whose coefficients are exact sums in Params); left alone they act
+// every stage with the same sign and drift the FP32 state.  They are removed
+// once per node, inside operations whose exact results are not yet rounded:
+// subtracting a correction below half an ulp from an already rounded smooth
+// field would round it away or double it in a fixed spatial pattern.  u: one
+// Newton step on rho u = j, with the momentum defect rho (ex, ey) folded into
+// the residual, so that rho * u reproduces j - defect rather than
+// rho * fl(j / rho).  Mass: dlt = defect / rho enters the equilibrium sum P'
+// as its starting value.  By symmetry of the tables only even-even (mass),
+// odd-even (x) and even-odd (y) monomials remain.  ux0, uy0 = j * (1 / rho)
+// on input; ux, uy corrected on output.
+template <typename CT, int N>
+__device__ __forceinline__ void fd_node_correct(const Params<CT> &p, CT drho, CT jx, CT jy, CT &ux, CT &uy,
+                                                CT &dlt)
+{
+    const CT ux0 = ux, uy0 = uy;
+    CT xp[N + 1], yp[N + 1];
+    xp[0] = yp[0] = CT(1);
+#pragma unroll
+    for (int n = 1; n <= N; ++n) {
+        xp[n] = xp[n - 1] * ux0;
+        yp[n] = yp[n - 1] * uy0;
+    }
+    CT dm = CT(0), ex = CT(0), ey = CT(0);
+#pragma unroll
+    for (int n = 0; n <= N; ++n)
+#pragma unroll
+        for (int m = 0; n + m <= N; ++m) {
+            if (n % 2 == 0 && m % 2 == 0 && n + m > 0) dm = fmaT(p.fd_m[n][m], xp[n] * yp[m], dm);
+            if (n % 2 == 1 && m % 2 == 0) {
+                ex = fmaT(p.fd_jx[n][m], xp[n] * yp[m], ex);
+                ey = fmaT(p.fd_jy[m][n], xp[m] * yp[n], ey);
+            }
+        }
+    const CT rho = p.rho0 + drho;  // the same value the equilibrium forms
+    const CT inv = CT(1) / rho;
+    const CT rx = fmaT(-rho, ex, fmaT(-rho, ux0, jx));
+    const CT ry = fmaT(-rho, ey, fmaT(-rho, uy0, jy));
+    ux = fmaT(rx, inv, ux0);
+    uy = fmaT(ry, inv, uy0);
+    dlt = fmaT(p.fd_w1 * drho, inv, dm);
+}
+
+// Order-N equilibrium of one population, shifted:  w_k [drho + rho P'(u)],
+// P' = sum_{1 <= n+m <= N} a_n b_m with a_n = He_n(xi_i) ux^n / n!,
+// b_m = He_m(xi_j) uy^m / m!, summed as C'_N + sum_n a_n (1 + C'_{N-n}),
+// C'_r = b_1 + ... + b_r (no O(1) term, so no cancellation) less the mass
+// defect dlt per unit rho.  The terms odd and even in xi_j (in the prefix
+// sums) and in xi_i (in the a_n sum) are accumulated apart and joined last:
+// mirrored populations then share their even part bit for bit, and the
+// roundings of the mass they carry do not drift one way (a single running
+// sum rounds the small even terms against a large odd one, with a bias of
+// ~10% of the rounding noise in D2Q36).  hx[n], hy[n] = He_n / n! at the
+// population's two roots.
+template <typename CT, int N>
+__device__ __forceinline__ CT fd_geq(CT wk, const CT (&hx)[N + 1], const CT (&hy)[N + 1], CT rho0, CT drho,
+                                     CT ux, CT uy, CT dlt)
+{
+    CT px[N + 1], py[N + 1];
+    px[1] = ux;
+    py[1] = uy;
+#pragma unroll
+    for (int n = 2; n <= N; ++n) {
+        px[n] = px[n - 1] * ux;
+        py[n] = py[n - 1] * uy;
+    }
+    CT ce = -dlt, co = CT(0);
+    CT cp[N];  // C'_0 .. C'_{N-1}
+    cp[0] = ce;
+#pragma unroll
+    for (int m = 1; m <= N; ++m) {
+        if (m % 2)
+            co = fmaT(hy[m], py[m], co);
+        else
+            ce = fmaT(hy[m], py[m], ce);
+        if (m < N) cp[m] = ce + co;
+    }
+#pragma unroll
+    for (int n = N; n >= 1; --n) {
+        if (n % 2)
+            co = fmaT(hx[n] * px[n], CT(1) + cp[N - n], co);
+        else
+            ce = fmaT(hx[n] * px[n], CT(1) + cp[N - n], ce);
+    }
+    const CT pp = ce + co;
+    return wk * fmaT(rho0 + drho, pp, drho);
+}
+
 // One 64 x (4 ROWS) tile (bx, by) of a Runge-Kutta stage, by a 256-thread
 // workgroup; with `diag` the diagnostics of the tile's input state go to
 // partial[diag_block].  Every face and node is evaluated by the same
@@ -265,47 +355,13 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         }
         if (diag) block_diag_store(acc, d.partial, diag_block);
 
-        // Moment-exact equilibrium.  The rounded tables give the equilibrium
-        // mass and momentum defects of relative size ~1e-8 (polynomials in u
-        // whose coefficients are exact sums in Params); left alone they act
-        // every stage with the same sign and drift the FP32 state.  They are
-        // removed here, once per node, inside operations whose exact results
-        // are not yet rounded: subtracting a correction below half an ulp from
-        // an already rounded smooth field would round it away or double it in
-        // a fixed spatial pattern.  u: one Newton step on rho u = j, with the
-        // momentum defect rho (ex, ey) folded into the residual, so that
-        // rho * u reproduces j - defect rather than rho * fl(j / rho).  Mass:
-        // defect / rho enters the equilibrium sum P' as its starting value
-        // (kept in LDS, thread-private, to spare registers).  By symmetry of the tables only even-even (mass), odd-even (x)
-        // and even-odd (y) monomials remain.
+        // moment-exact equilibrium corrections (fd_node_correct); the mass
+        // defect goes to LDS, thread-private, to spare registers
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            const CT ux = uxv[r], uy = uyv[r];
-            CT xp[N + 1], yp[N + 1];
-            xp[0] = yp[0] = CT(1);
-#pragma unroll
-            for (int n = 1; n <= N; ++n) {
-                xp[n] = xp[n - 1] * ux;
-                yp[n] = yp[n - 1] * uy;
-            }
-            CT dm = CT(0), ex = CT(0), ey = CT(0);
-#pragma unroll
-            for (int n = 0; n <= N; ++n)
-#pragma unroll
-                for (int m = 0; n + m <= N; ++m) {
-                    if (n % 2 == 0 && m % 2 == 0 && n + m > 0) dm = fmaT(p.fd_m[n][m], xp[n] * yp[m], dm);
-                    if (n % 2 == 1 && m % 2 == 0) {
-                        ex = fmaT(p.fd_jx[n][m], xp[n] * yp[m], ex);
-                        ey = fmaT(p.fd_jy[m][n], xp[m] * yp[n], ey);
-                    }
-                }
-            const CT rho = p.rho0 + drho[r];  // the same value the node update forms
-            const CT inv = CT(1) / rho;
-            const CT rx = fmaT(-rho, ex, fmaT(-rho, ux, jx[r]));
-            const CT ry = fmaT(-rho, ey, fmaT(-rho, uy, jy[r]));
-            uxv[r] = fmaT(rx, inv, ux);
-            uyv[r] = fmaT(ry, inv, uy);
-            dltl[r * kFdThreads + tid] = fmaT(p.fd_w1 * drho[r], inv, dm);
+            CT dlt;
+            fd_node_correct<CT, N>(p, drho[r], jx[r], jy[r], uxv[r], uyv[r], dlt);
+            dltl[r * kFdThreads + tid] = dlt;
         }
     }
 
@@ -404,6 +460,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         const CT wk = p.w[k];
         const CT vxs = vxk * p.inv_ds, vys = vyk * p.inv_ds;
         CT hx[N + 1], hy[N + 1];
+        hx[0] = hy[0] = CT(1);
 #pragma unroll
         for (int n = 1; n <= N; ++n) {
             hx[n] = p.hc[qi][n];
@@ -415,45 +472,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             const CT g = L[c0 + r * kLX];
             const CT dfx = (vxk != CT(0)) ? xface[tr * kXFaceStride + lx + 1] - xface[tr * kXFaceStride + lx] : CT(0);
 
-            // order-N equilibrium, shifted:  w_k [drho + rho P'(u)],
-            // P' = sum_{1 <= n+m <= N} a_n b_m with a_n = He_n(xi_i) ux^n / n!,
-            // b_m = He_m(xi_j) uy^m / m!, summed as C'_N + sum_n a_n (1 + C'_{N-n}),
-            // C'_r = b_1 + ... + b_r (no O(1) term, so no cancellation) less the
-            // mass defect per unit rho.  The terms odd and even in xi_j (in the
-            // prefix sums) and in xi_i (in the a_n sum) are accumulated apart
-            // and joined last: mirrored populations then share their even part
-            // bit for bit, and the roundings of the mass they carry do not
-            // drift one way (a single running sum rounds the small even terms
-            // against a large odd one, with a bias of ~10% of the rounding
-            // noise in D2Q36).
-            CT px[N + 1], py[N + 1];
-            px[1] = uxv[r];
-            py[1] = uyv[r];
-#pragma unroll
-            for (int n = 2; n <= N; ++n) {
-                px[n] = px[n - 1] * uxv[r];
-                py[n] = py[n - 1] * uyv[r];
-            }
-            CT ce = -dltl[r * kFdThreads + tid], co = CT(0);
-            CT cp[N];  // C'_0 .. C'_{N-1}
-            cp[0] = ce;
-#pragma unroll
-            for (int m = 1; m <= N; ++m) {
-                if (m % 2)
-                    co = fmaT(hy[m], py[m], co);
-                else
-                    ce = fmaT(hy[m], py[m], ce);
-                if (m < N) cp[m] = ce + co;
-            }
-#pragma unroll
-            for (int n = N; n >= 1; --n) {
-                if (n % 2)
-                    co = fmaT(hx[n] * px[n], CT(1) + cp[N - n], co);
-                else
-                    ce = fmaT(hx[n] * px[n], CT(1) + cp[N - n], ce);
-            }
-            const CT pp = ce + co;
-            const CT geq = wk * fmaT(p.rho0 + drho[r], pp, drho[r]);
+            const CT geq = fd_geq<CT, N>(wk, hx, hy, p.rho0, drho[r], uxv[r], uyv[r], dltl[r * kFdThreads + tid]);
 
             const CT adv = fmaT(vxs, dfx, vys * dfy[r]);
             const CT Lk = -fmaT(g - geq, inv_tau, adv);

@@ -150,6 +150,12 @@ hipError_t launch_cs_step(const T *src, T *dst, const Params<typename Arith<T>::
 template <typename T>
 hipError_t launch_fd_stage(const T *src, const T *gn, T *out, int stage, const Params<typename Arith<T>::type> &p,
                            const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int rows = 8);
+// Pointwise stages of the implicit-explicit FD step: which = 0 relaxes g
+// into a_buf; which = 1 turns (y in b_buf, g, f1 in a_buf) into (f2 in
+// b_buf, the last stage's base in a_buf).  dt_over_tau = dt / tau.
+template <typename T>
+hipError_t launch_fd_imex(int which, T *a_buf, const T *g, T *b_buf, const Params<typename Arith<T>::type> &p,
+                          double dt_over_tau, hipStream_t s);
 int cs_diag_blocks(int Nx, int Ny);
 int fd_diag_blocks(int Nx, int Ny);
 

@@ -18,6 +18,7 @@ struct lb_sim {
     int model = 0;
     lbm::Prec prec = lbm::P32;
     bool cs = true;
+    bool imex = false;  // FD: implicit-explicit time stepping (LB_IMEX)
     int Nx = 0, Ny = 0, K = 0, Q = 0, N = 0;
     double tau = 0, dt = 0, ds = 0;
     lbm::ModelInfo mi{};

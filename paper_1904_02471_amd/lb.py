@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LB_CS_D2Q9, LB_FD_D2Q9, LB_FD_D2Q16, LB_FD_D2Q25, LB_FD_D2Q36 = 0, 1, 2, 3, 4
 LB_FP32, LB_FP16_SHIFTED, LB_FP64 = 0, 1 << 8, 2 << 8
+LB_IMEX = 1 << 10
 LB_OK, LB_EINVAL, LB_ECFL, LB_ESTIFF, LB_ENOMEM, LB_EDEVICE, LB_ENAN, LB_EBUSY, LB_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_FD_D2Q36: 6}
 
@@ -116,10 +117,12 @@ class Sim:
     methods (same names without the prefix) and the module-level lb_*
     functions below."""
 
-    def __init__(self, model, Nx, Ny, tau, dt, ds, N=2, precision=LB_FP32):
+    def __init__(self, model, Nx, Ny, tau, dt, ds, N=2, precision=LB_FP32, imex=False):
         self.model, self.Nx, self.Ny, self.N = int(model), int(Nx), int(Ny), int(N)
         self.tau, self.dt, self.ds, self.precision = float(tau), float(dt), float(ds), int(precision)
-        h = _lib.lb_create(self.model | self.precision, self.Nx, self.Ny, self.tau, self.dt, self.ds, self.N)
+        self.imex = bool(imex)
+        flags = self.model | self.precision | (LB_IMEX if self.imex else 0)
+        h = _lib.lb_create(flags, self.Nx, self.Ny, self.tau, self.dt, self.ds, self.N)
         if not h:
             raise LBError(_lib.lb_last_error(), "lb_create")
         self._h = h

@@ -66,6 +66,9 @@ def test_d2q9_tables():
     ((lb.LB_FD_D2Q16, 8, 8, 1e-3, 1e-3, 0.1, 0), lb.LB_EINVAL),
     ((lb.LB_FD_D2Q16, 8, 8, 1.0, 0.05, 0.1, 3), lb.LB_ECFL),    # 2.334 * 0.05 / 0.1 > 1
     ((lb.LB_FD_D2Q16, 8, 8, 1e-3, 2e-3, 0.1, 3), lb.LB_ESTIFF),  # dt > tau
+    ((lb.LB_CS_D2Q9 | lb.LB_IMEX, 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),  # IMEX is FD only
+    ((lb.LB_FD_D2Q16 | lb.LB_IMEX, 8, 8, 1e-3, 0.05, 0.1, 3), lb.LB_ECFL),  # IMEX keeps the CFL bound
+    ((lb.LB_FD_D2Q16 | (1 << 11), 8, 8, 1e-3, 1e-4, 0.1, 3), lb.LB_EINVAL),  # unknown flag
     ((7, 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),                # unknown model
     ((lb.LB_CS_D2Q9 | (3 << 8), 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),
     ((lb.LB_CS_D2Q9, 8, 8, float("nan"), 1.0, 1.0, 2), lb.LB_EINVAL),
@@ -116,3 +119,13 @@ def test_separable_patterns_match_the_initial_fields(kind, Nx, Ny):
         _, _, _, (px, py) = workloads.shear_wave(Nx, Ny, 1.0, kind[-1])
     np.testing.assert_allclose(np.outer(ay, ax), px, atol=1e-15)
     np.testing.assert_allclose(np.outer(by, bx), py, atol=1e-15)
+
+
+def test_imex_lifts_the_stiffness_bound():
+    """dt > tau passes validation with LB_IMEX (creation then proceeds to the
+    device, which this host does not have, or succeeds on a GPU host)."""
+    h = lb._lib.lb_create(lb.LB_FD_D2Q16 | lb.LB_IMEX, 8, 8, 1e-3, 2e-3, 0.1, 3)
+    if h:
+        lb._lib.lb_destroy(h)
+    else:
+        assert lb.lb_last_error() not in (lb.LB_ESTIFF, lb.LB_EINVAL, lb.LB_ECFL)
