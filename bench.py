@@ -104,8 +104,9 @@ def kernel_traffic(kernel, n):
 
 
 def cpu_baseline(every):
-    """FP64 oracle on a bounded sample of the same workload: CS D2Q9 512^2 x 16
-    steps and FD D2Q16 256^2 x 4 steps, diagnostics every `every` steps."""
+    """FP64 oracle on a bounded sample of the same workload (about 15 s of one
+    core): CS D2Q9 512^2 x 48 steps and FD D2Q16 256^2 x 12 steps, diagnostics
+    every `every` steps."""
     import oracle
     from paper_1904_02471_amd import units, workloads
 
@@ -126,11 +127,11 @@ def cpu_baseline(every):
             s.step(1)
         return (time.perf_counter() - t0) / (n * n * steps)
 
-    t_cs = run(oracle.CS_D2Q9, 512, 16)
-    t_fd = run(oracle.FD_D2Q16, 256, 4)
+    t_cs = run(oracle.CS_D2Q9, 512, 48)
+    t_fd = run(oracle.FD_D2Q16, 256, 12)
     return {"value": 1e-6 / (t_cs + t_fd), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "FP64 C oracle, single thread: CS D2Q9 TGV 512x512 x 16 steps (%.3f MLUPS) + "
-                      "FD D2Q16 TGV 256x256 x 4 steps (%.4f MLUPS), diagnostics every %d steps; value = "
+            "sample": "FP64 C oracle, single thread: CS D2Q9 TGV 512x512 x 48 steps (%.3f MLUPS) + "
+                      "FD D2Q16 TGV 256x256 x 12 steps (%.4f MLUPS), diagnostics every %d steps; value = "
                       "1 / (t_cs + t_fd) per node" % (1e-6 / t_cs, 1e-6 / t_fd, every)}
 
 

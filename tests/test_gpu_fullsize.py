@@ -33,27 +33,62 @@ def bench_fd():
     return g, (r, ux, uy), dict(tau=tau, dt=dt, ds=ds, N=3), 9   # reach: 3 stages x 3 nodes
 
 
-@pytest.mark.parametrize("which,nsteps", [("cs", 3), ("fd", 2)])
-def test_sampled_nodes_full_size(which, nsteps):
+def tgv4096_cs(prec):
+    n = 4096
+    g = lb.Sim(lb.LB_CS_D2Q9, n, n, 0.55, 1.0, 1.0, 2, precision=prec)
+    r, ux, uy, _ = workloads.taylor_green(n, n, 0.01, 1.0 / 3.0)
+    g.init(r, ux, uy)
+    return g, (r, ux, uy), dict(tau=0.55, dt=1.0, ds=1.0, N=2), 1
+
+
+def tgv2048_fd36():
+    ds = 1.0 / N
+    tau = 5e-4
+    dt = units.fd_time_step(tau, ds, lb.lb_model_info(lb.LB_FD_D2Q36)[0].max(), 0.5)
+    g = lb.Sim(lb.LB_FD_D2Q36, N, N, tau, dt, ds, 4, precision=lb.LB_FP32)
+    r, ux, uy, _ = workloads.taylor_green(N, N, 0.01, 1.0)
+    g.init(r, ux, uy)
+    return g, (r, ux, uy), dict(tau=tau, dt=dt, ds=ds, N=4), 9
+
+
+CASES = {
+    "cs": (bench_cs, 3, lb.LB_FP32, False),
+    "fd": (bench_fd, 2, lb.LB_FP32, False),
+    # the timed configuration: autotuned launch shapes, graph-replayed runs
+    "cs_tuned": (bench_cs, 10, lb.LB_FP32, True),
+    "fd_tuned": (bench_fd, 5, lb.LB_FP32, True),
+    # the 4096^2 vortex in FP32 and FP16-shifted storage, D2Q36 at 2048^2
+    "cs4096_fp32": (lambda: tgv4096_cs(lb.LB_FP32), 10, lb.LB_FP32, True),
+    "cs4096_fp16": (lambda: tgv4096_cs(lb.LB_FP16_SHIFTED), 6, lb.LB_FP16_SHIFTED, False),
+    "fd36": (tgv2048_fd36, 5, lb.LB_FP32, True),
+}
+
+
+@pytest.mark.parametrize("which", list(CASES))
+def test_sampled_nodes_full_size(which):
+    build, nsteps, prec, tuned = CASES[which]
     print("case: full size sampled nodes", which, nsteps, flush=True)
-    g, (r, ux, uy), prm, reach = bench_cs() if which == "cs" else bench_fd()
+    g, (r, ux, uy), prm, reach = build()
+    if tuned:
+        g.autotune(3)
     g.step(nsteps)
     f = g.get_state()
+    Nn = g.Nx
     R = reach * nsteps + 2
     W = 2 * R + 1
     rng = np.random.default_rng(2048)
-    pts = [(0, 0), (N - 1, N - 1), (0, N - 1), (N - 1, 0), (1023, 1024)] + \
-        [tuple(p) for p in rng.integers(0, N, (10, 2))]
+    pts = [(0, 0), (Nn - 1, Nn - 1), (0, Nn - 1), (Nn - 1, 0), (Nn // 2 - 1, Nn // 2)] + \
+        [tuple(p) for p in rng.integers(0, Nn, (10, 2))]
     worst = 0.0
     for (x, y) in pts:
-        xs = (np.arange(x - R, x + R + 1)) % N
-        ys = (np.arange(y - R, y + R + 1)) % N
+        xs = (np.arange(x - R, x + R + 1)) % Nn
+        ys = (np.arange(y - R, y + R + 1)) % Nn
         o = oracle.OracleSim(ORACLE_MODEL[g.model], W, W, prm["tau"], prm["dt"], prm["ds"], prm["N"])
         o.init(r[np.ix_(ys, xs)], ux[np.ix_(ys, xs)], uy[np.ix_(ys, xs)])
         o.step(nsteps)
         fo = o.get_state()[:, R, R]
         fg = f[:, y, x]
-        tol = tolerance(lb.LB_FP32, nsteps, fo[:, None, None], g.w, 1.0)
+        tol = tolerance(prec, nsteps, fo[:, None, None], g.w, 1.0)
         err = float(np.max(np.abs(fg - fo)))
         worst = max(worst, err)
         assert err <= tol, (x, y, err, tol)
