@@ -19,7 +19,9 @@
 // terms:
 //
 //   A workgroup of 256 threads owns a 64 x 32 tile; thread (lx, wy) owns
-//   column lx and the 8 rows 8 wy .. 8 wy + 7.
+//   column lx and the 8 rows 8 wy .. 8 wy + 7 (the canonical geometry; the
+//   tile height is a template parameter, 64 x 16 with 4 rows per thread is
+//   the other choice of the autotuner, with 4-face x segments).
 //   1. moments: the thread gathers the K values of its 8 nodes and keeps
 //      drho, u_x, u_y per node.
 //   2. loop over the populations k; the tile of population k with a 3-node
@@ -225,9 +227,8 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 {
     using CT = typename Arith<T>::type;
     using G = FdGeom<ROWS>;
-    constexpr int kRows = G::kRows, kTY = G::kTY, kLY = G::kLY, kTileElems = G::kTileElems;
+    constexpr int kRows = G::kRows, kTY = G::kTY, kTileElems = G::kTileElems;
     constexpr int kLoadsPerThread = G::kLoadsPerThread, kSeg = G::kSeg;
-    (void)kLY;
     __shared__ CT tile[2][kTileElems];
     __shared__ CT xface[kTY * kXFaceStride];
     // FP32 storage: tiles and the Runge-Kutta base values are copied from
