@@ -111,20 +111,32 @@ __device__ __forceinline__ void cs_diag_node(DiagAcc &acc, const CsMoments<CT> &
     if (d.ax) acc.v[4] += (double)(m.ux * (d.ax[x] * pay) + m.uy * (d.bx[x] * pby));
 }
 
-// Random bits of the stochastic FP16 rounding: one counter-based draw per
-// node and step, advanced once per population in the order 0..8 (the same
-// in every path, so results do not depend on the path).
+// Random bits of the stochastic FP16 rounding: 13 per population, from one
+// counter-based word per node and its xorshift successors (populations 2i
+// and 2i+1 take the top and the bottom 13 bits of word i), drawn in the
+// order 0..8 in every path, so results do not depend on the path.
 template <typename T>
 struct CsRand {
     uint32_t s = 0;
+    bool lo = false;
     __device__ __forceinline__ CsRand(int node, unsigned salt)
     {
         if constexpr (std::is_same<T, __half>::value) s = mix32((uint32_t)node, salt);
     }
     __device__ __forceinline__ uint32_t next()
     {
-        if constexpr (std::is_same<T, __half>::value) s = xorshift32(s);
-        return s;
+        if constexpr (std::is_same<T, __half>::value) {
+            uint32_t r;
+            if (lo) {
+                r = s & 0x1fffu;
+                s = xorshift32(s);
+            } else {
+                r = s >> 19;
+            }
+            lo = !lo;
+            return r;
+        }
+        return 0u;
     }
 };
 
@@ -133,11 +145,6 @@ __device__ __forceinline__ typename Arith<T>::type to_ct(T v);
 template <> __device__ __forceinline__ float to_ct<float>(float v) { return v; }
 template <> __device__ __forceinline__ float to_ct<__half>(__half v) { return __half2float(v); }
 template <> __device__ __forceinline__ double to_ct<double>(double v) { return v; }
-
-// Rounding of a stepped value to the storage type (stochastic for FP16).
-__device__ __forceinline__ float to_storage(float v, uint32_t, float *) { return v; }
-__device__ __forceinline__ double to_storage(double v, uint32_t, double *) { return v; }
-__device__ __forceinline__ __half to_storage(float v, uint32_t r, __half *) { return half_sr(v, r); }
 
 // A chunk of W consecutive stored values, loaded and stored as one access:
 // 16 bytes (4 FP32 or 2 FP64 values) or, for FP16, 8 bytes (4 values, which
@@ -282,6 +289,7 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
 {
     using CT = typename Arith<T>::type;
     constexpr int W = Chunk<T>::W;
+    static_assert(!std::is_same<T, __half>::value || W % 2 == 0, "FP16 chunks convert node pairs");
     const int Nx = p.Nx, nch = Nx / W;
     const int ym = (y == 0) ? p.Ny - 1 : y - 1;
     const int yp = (y == p.Ny - 1) ? 0 : y + 1;
@@ -329,6 +337,7 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
             r7 = rn[7 * P + xp];
         }
         Chunk<T> out[9];
+        float held[9];  // FP16: the even node's values awaiting their pair
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             CT g[9], o[9];
@@ -344,7 +353,18 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
             const CsMoments<CT> m = cs_collide(g, o, c);
             CsRand<T> rnd(y * Nx + x + j, p.salt);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) out[k].set(j, to_storage(o[k], rnd.next(), (T *)nullptr));
+            for (int k = 0; k < 9; ++k) {
+                if constexpr (std::is_same<T, __half>::value) {
+                    // FP16: converted in pairs of nodes, one packed conversion each
+                    const float v = sr16_pre(o[k], rnd.next());
+                    if (j & 1)
+                        out[k].w[j >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(held[k], v));
+                    else
+                        held[k] = v;
+                } else {
+                    out[k].set(j, o[k]);
+                }
+            }
             if (DIAG) cs_diag_node(acc, m, d, x + j, pay, pby);
         }
 #pragma unroll

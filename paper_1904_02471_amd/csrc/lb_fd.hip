@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void fd_imex_relax_kernel(const T *__restrict_
     for (int k = 0; k < p.K; ++k) {
         const CT h = ld(g + k * P + o);
         rb = xorshift32(rb);
-        store_state(out + k * P + o, fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa, rb);
+        store_state(out + k * P + o, fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa, rb >> 19);
     }
 }
 
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(256) void fd_imex_mid_kernel(T *__restrict__ yb, co
         const CT f2 = fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa;
         const CT b = fmaT(CT(2), f1, h - f) - f2;
         rb = xorshift32(rb);
-        store_state(yb + k * P + o, f2, rb);
+        store_state(yb + k * P + o, f2, rb >> 19);
         rb = xorshift32(rb);
-        store_state(f1b + k * P + o, b, rb);
+        store_state(f1b + k * P + o, b, rb >> 19);
     }
 }
 

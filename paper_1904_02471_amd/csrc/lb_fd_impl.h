@@ -490,7 +490,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 uint32_t rb = 0;
                 if constexpr (std::is_same<T, __half>::value)
                     rb = mix32((uint32_t)((gy0 + r) * Nx + gx), p.salt ^ ((uint32_t)k * 0x632be5abu));
-                store_state(out + k * P + node_off(r), res, rb);
+                store_state(out + k * P + node_off(r), res, rb >> 19);
             }
         }
 

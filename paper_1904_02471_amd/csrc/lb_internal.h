@@ -66,29 +66,39 @@ __device__ __forceinline__ void store_from(double *p, double v) { *p = v; }
 __device__ __forceinline__ void store_from(float *p, double v) { *p = (float)v; }
 __device__ __forceinline__ void store_from(__half *p, double v) { *p = __builtin_bit_cast(__half, (_Float16)v); }
 
-// Stochastic rounding of an FP32 value to FP16 with 32 random bits r: the
-// bits of the FP32 pattern below the FP16 ulp (13 in the normal range, more
-// in the subnormal range) get r added and are then cleared, so the value
-// rounds up with probability equal to its position between the two FP16
-// neighbours; the result is exact in FP16, so the final conversion does not
-// round again.  Below the smallest subnormal (2^-24) the choice is between 0
-// and 2^-24.  Unbiased: a state that changes by less than an FP16 ulp per
-// step still evolves correctly on average, where round-to-nearest would hold
-// it fixed.
-__device__ __forceinline__ __half half_sr(float v, uint32_t r)
+// Stochastic rounding of an FP32 value to FP16 with 13 random bits r13
+// (0..8191).  sr16_pre returns an FP32 value whose conversion toward zero to
+// FP16 is the rounded value: v moves away from zero by r13 units of 2^-13 of
+// the FP16 step at v (2^-10 of its power of two in the FP16 normal range,
+// 2^-24 below 2^-14); in the FP16 normal range that is a whole number of
+// FP32 ulps of v, so the sum is exact.  The value then passes the upper FP16
+// neighbour with probability equal to its position between the two
+// neighbours, and the truncation keeps the lower one otherwise: exactly
+// unbiased in the FP16 normal range.  Below 2^-14 the FP32 bits of v finer
+// than 2^-37 are not randomised, which biases the result toward zero by less
+// than 2^-13 of an FP16 step (2^-37 absolute); below 2^-24 the choice is
+// between 0 and 2^-24.  A state that changes by less than an FP16 step per
+// time step thus still evolves correctly on average, where round-to-nearest
+// would hold it fixed.  No branches: every lane takes the same instructions
+// whatever the range of its value.
+__device__ __forceinline__ float sr16_pre(float v, uint32_t r13)
 {
     const uint32_t b = __float_as_uint(v);
-    uint32_t a = b & 0x7fffffffu;
-    if (a >= 0x38800000u) {  // |v| >= 2^-14
-        a = (a + (r & 0x1fffu)) & ~0x1fffu;
-    } else if (a >= 0x33800000u) {  // 2^-24 <= |v| < 2^-14: FP16 grid 2^-24
-        const uint32_t m = (1u << (126u - (a >> 23))) - 1u;  // 14..23 bits
-        a = (a + (r & m)) & ~m;
-    } else {
-        const float p = __uint_as_float(a) * 16777216.0f;  // |v| / 2^-24, exact
-        a = ((float)(r >> 8) * (1.0f / 16777216.0f) < p) ? 0x33800000u : 0u;
-    }
-    return __float2half_rn(__uint_as_float(a | (b & 0x80000000u)));
+    // 2^-13 of the FP16 step at v: exponent max(e, 113) - 23, the sign of v
+    const uint32_t e = max(b & 0x7f800000u, 113u << 23) - (23u << 23);
+    return __builtin_fmaf((float)r13, __uint_as_float((b & 0x80000000u) | e), v);
+}
+
+// Two stochastically rounded values as one packed FP16 pair (a in the low half).
+__device__ __forceinline__ uint32_t half2_sr_bits(float a, uint32_t ra13, float b, uint32_t rb13)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(sr16_pre(a, ra13), sr16_pre(b, rb13)));
+}
+
+__device__ __forceinline__ __half half_sr(float v, uint32_t r13)
+{
+    const uint32_t w = half2_sr_bits(v, r13, 0.0f, 0u);
+    return __builtin_bit_cast(__half, (unsigned short)(w & 0xffffu));
 }
 
 // Counter-based random bits (a 32-bit integer mixer) for (key, salt).
@@ -123,10 +133,10 @@ inline unsigned mix_host(unsigned x)
 }
 
 // Store of a stepped state value: FP16 storage rounds stochastically with the
-// given random bits, the other storage types round to nearest.
+// given 13 random bits, the other storage types round to nearest.
 __device__ __forceinline__ void store_state(float *p, float v, uint32_t) { *p = v; }
 __device__ __forceinline__ void store_state(double *p, double v, uint32_t) { *p = v; }
-__device__ __forceinline__ void store_state(__half *p, float v, uint32_t r) { *p = half_sr(v, r); }
+__device__ __forceinline__ void store_state(__half *p, float v, uint32_t r13) { *p = half_sr(v, r13); }
 
 template <typename T> struct Arith { using type = float; };
 template <> struct Arith<double> { using type = double; };

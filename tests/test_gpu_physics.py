@@ -149,9 +149,9 @@ def test_taylor_green_4096_fp16():
     populations is ~5e-4 of them: round-to-nearest freezes the state between
     ulps (fitted nu 15% off).  Stochastic rounding is unbiased, and what is
     left is its noise: ~1e-6 of momentum per node and step, which projects
-    onto the vortex as a random walk whose least-squares slope error is a few
-    1e-3 of the decay rate over 5000 steps.  Bound: 5e-3 (the FP32 storage
-    case above meets 1e-3)."""
+    onto the vortex as a random walk whose least-squares slope error is of
+    order 1e-3 of the decay rate over 5000 steps (1.1e-3 measured).  Bound:
+    5e-3 (the FP32 storage case above meets 1e-3)."""
     print("case: tgv 4096 fp16", flush=True)
     nu_fit, nu = tgv4096_nu(lb.LB_FP16_SHIFTED)
     print("nu fp16 %.7f analytic %.7f" % (nu_fit, nu), flush=True)
