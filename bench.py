@@ -10,8 +10,10 @@ storage.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: MLUPS of the whole step (node updates per second:
 one update advances a node by one CS step and one FD step), per-model MLUPS
-and HBM fractions, the roofline of the dominant kernel (the FD stage) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+and HBM fractions, the roofline of the dominant kernel (the FD stage), the
+CS step at 4096^2 with FP32 and FP16-shifted storage (states larger than the
+last-level cache, so those byte rates are HBM rates), the serving stream,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -49,6 +51,8 @@ def parse():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--sample-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cache-free", action="store_true",
+                    help="skip the 4096^2 CS FP32 / FP16 runs (state larger than the last-level cache)")
     ap.add_argument("--only", choices=["cs", "fd"], default=None,
                     help="time one model alone (profiling runs); the JSON line is then per model")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -77,6 +81,37 @@ def make_sims(lb, workloads, units, n, stream):
     fd.init(r, ux, uy)
     fd.set_probe(ax, ay, bx, by)
     return cs, fd, {"tau_fd": tau_fd, "dt_fd": dt_fd}
+
+
+def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
+    """CS D2Q9 plain steps on the n x n Taylor-Green vortex (tau = 0.55) with
+    FP32 and FP16-shifted storage: at 4096^2 the two state buffers (1.2 GB /
+    0.6 GB) exceed the 256 MB last-level cache, so the byte rate is the HBM
+    rate.  Autotuned launch shapes; plain steps as the library runs them."""
+    import torch
+    out = {"grid": [n, n], "steps": steps}
+    for name, prec, s in (("fp32", lb.LB_FP32, 4), ("fp16_shifted", lb.LB_FP16_SHIFTED, 2)):
+        sim = lb.Sim(lb.LB_CS_D2Q9, n, n, 0.55, 1.0, 1.0, 2, precision=prec)
+        sim.set_stream(stream.cuda_stream)
+        r, ux, uy, _ = workloads.taylor_green(n, n, 0.01, 1.0 / 3.0)
+        sim.init(r, ux, uy)
+        del r, ux, uy
+        threads = sim.autotune(10)[0]
+        sim.step(warmup)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            sim.step(steps)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        gbs = 2 * 9 * s * n * n / (ms * 1e-3) / 1e9
+        out[name] = {"ms_per_step": round(ms, 5), "mlups": round(n * n / (ms * 1e-3) / 1e6, 1),
+                     "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_node_step": 18 * s, "cs_threads": threads}
+        sim.destroy()
+    return out
 
 
 def source_digest(files):
@@ -232,7 +267,8 @@ def main():
     cs.series_reserve(cap)
     fd.series_reserve(cap)
     # launch shapes of the plain steps chosen by the library's autotuner
-    tuned = {"cs_threads": cs.autotune(10)[0], "fd_tile_rows": fd.autotune(5)[1]}
+    fd_tuned = fd.autotune(5)
+    tuned = {"cs_threads": cs.autotune(10)[0], "fd_tile_rows": fd_tuned[1], "fd_tile_rows_later_stages": fd_tuned[2]}
     run_cs = args.only in (None, "cs")
     run_fd = args.only in (None, "fd")
 
@@ -341,9 +377,14 @@ def main():
         ms = a.elapsed_time(b) / 20
         line["copy_calibration"] = {"bytes_moved": 2 * src.numel() * 4, "ms": round(ms, 5),
                                     "gbs": round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
-    if args.serving_requests > 0:
+    if args.only is None and not args.no_cache_free:
         cs.destroy()
         fd.destroy()
+        line["cs_d2q9_4096"] = cache_free_cs(lb, workloads, stream)
+    if args.serving_requests > 0:
+        if args.only is not None or args.no_cache_free:
+            cs.destroy()
+            fd.destroy()
         line["serving"] = serving_bench(args.serving_requests, every)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(every)

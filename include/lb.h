@@ -196,17 +196,20 @@ int lb_set_graph_steps(lb_sim *sim, int steps);
  * each candidate on the handle's own buffers, leaving the state unchanged,
  * and keeps the fastest: CS (vector row form only) workgroup sizes of 256,
  * 512 and 1024 threads against one chunk per thread; FD tiles of 64 x 32 and
- * 64 x 16 nodes.  Synchronises the stream.  LB_ESTATE before lb_init,
- * LB_EINVAL for reps outside [1, 1000]. */
+ * 64 x 16 nodes, chosen separately for the first Runge-Kutta stage and for
+ * the later stages (which also read the step's base state, so their kernels
+ * hold more registers and LDS).  Synchronises the stream.  LB_ESTATE before
+ * lb_init, LB_EINVAL for reps outside [1, 1000]. */
 int lb_autotune(lb_sim *sim, int reps);
 
 /* Set the plain-step launch shapes directly: cs_threads 0 (one chunk per
- * thread) or a multiple of 64 up to 1024; fd_rows 8 (64 x 32 tiles) or 4
- * (64 x 16).  LB_EINVAL otherwise. */
-int lb_set_tuning(lb_sim *sim, int cs_threads, int fd_rows);
+ * thread) or a multiple of 64 up to 1024; fd_rows (first FD stage) and
+ * fd_rows_rest (later FD stages, the last IMEX stage included) 8 (64 x 32
+ * tiles) or 4 (64 x 16).  LB_EINVAL otherwise. */
+int lb_set_tuning(lb_sim *sim, int cs_threads, int fd_rows, int fd_rows_rest);
 
 /* The current plain-step launch shapes (host ints). */
-int lb_get_tuning(const lb_sim *sim, int *cs_threads, int *fd_rows);
+int lb_get_tuning(const lb_sim *sim, int *cs_threads, int *fd_rows, int *fd_rows_rest);
 
 /* Launch on a caller-owned HIP stream (hipStream_t passed as void*; NULL
  * means the library's own stream).  The caller keeps the stream alive. */

@@ -212,11 +212,11 @@ hipError_t step_once(lb_sim *s, bool with_diag)
             e = launch_fd_imex<T>(0, a, g, nullptr, p, r, s->stream);
             if (e == hipSuccess) e = launch_fd_stage<T>(a, nullptr, b, 1, p, dp, s->stream, dp ? 8 : s->fd_rows);
             if (e == hipSuccess) e = launch_fd_imex<T>(1, a, g, b, p, r, s->stream);
-            if (e == hipSuccess) e = launch_fd_stage<T>(b, a, g, 4, p, nullptr, s->stream, s->fd_rows);
+            if (e == hipSuccess) e = launch_fd_stage<T>(b, a, g, 4, p, nullptr, s->stream, s->fd_rows_rest);
         } else {
             e = launch_fd_stage<T>(g, nullptr, a, 1, p, dp, s->stream, dp ? 8 : s->fd_rows);
-            if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, s->fd_rows);
-            if (e == hipSuccess) e = launch_fd_stage<T>(b, g, g, 3, p, nullptr, s->stream, s->fd_rows);
+            if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, s->fd_rows_rest);
+            if (e == hipSuccess) e = launch_fd_stage<T>(b, g, g, 3, p, nullptr, s->stream, s->fd_rows_rest);
         }
     }
     if (e == hipSuccess) ++s->steps;
@@ -294,23 +294,26 @@ hipError_t plain_steps(lb_sim *s, long long n)
 // Autotuning of the plain-step launch shapes.  Candidates are timed on the
 // handle's own buffers with launches that leave the state untouched: a CS
 // step from the current buffer into the other one (which the next step
-// overwrites), FD stages 1 and 2 into the stage buffers A and B.
+// overwrites), FD stage 1 into the stage buffer A or stage 2 from A into B.
+// fd_stage selects the FD stage timed (its tile rows fd_rows).
 template <typename T>
-hipError_t time_candidate(lb_sim *s, int cs_threads, int fd_rows, int reps, float *ms)
+hipError_t time_candidate(lb_sim *s, int cs_threads, int fd_stage, int fd_rows, int reps, float *ms)
 {
     using CT = typename Arith<T>::type;
     const Params<CT> p = make_params<CT>(s);
+    T *g = s->cs ? nullptr : bufp<T>(s, 0), *a = s->cs ? nullptr : bufp<T>(s, 1), *b = s->cs ? nullptr : bufp<T>(s, 2);
     auto launch = [&]() -> hipError_t {
         if (s->cs) return launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, nullptr, s->stream, cs_threads);
-        T *g = bufp<T>(s, 0), *a = bufp<T>(s, 1), *b = bufp<T>(s, 2);
-        hipError_t e = launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, fd_rows);
-        if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, fd_rows);
-        return e;
+        if (fd_stage == 1) return launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, fd_rows);
+        return launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, fd_rows);
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess) e = launch();  // warm-up
+    // warm-up; a later stage reads A, which a first stage fills
+    if (e == hipSuccess && !s->cs && fd_stage != 1)
+        e = launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, 8);
+    if (e == hipSuccess) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
     for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
@@ -760,51 +763,62 @@ int lb_autotune(lb_sim *s, int reps)
     if (!s || reps < 1 || reps > 1000) return fail(LB_EINVAL);
     if (!s->ready) return fail(LB_ESTATE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
-    std::vector<std::pair<int, int>> cand;  // (cs_threads, fd_rows)
+    // the fastest of the candidates of one choice (cs_threads or the tile
+    // rows of one FD stage); the first candidate when there is no choice
+    auto pick = [&](const std::vector<int> &cand, int fd_stage, int *out) -> hipError_t {
+        if (cand.size() < 2) return hipSuccess;
+        float best = 0.0f;
+        for (size_t i = 0; i < cand.size(); ++i) {
+            float ms = 0.0f;
+            hipError_t e = with_type(s, [&](auto *tag) {
+                using T = std::remove_pointer_t<decltype(tag)>;
+                return s->cs ? time_candidate<T>(s, cand[i], 0, 8, reps, &ms)
+                             : time_candidate<T>(s, 0, fd_stage, cand[i], reps, &ms);
+            });
+            if (e != hipSuccess) return e;
+            if (i == 0 || ms < best) {
+                best = ms;
+                *out = cand[i];
+            }
+        }
+        return hipSuccess;
+    };
+    int cs_threads = s->cs_threads, rows1 = s->fd_rows, rows_rest = s->fd_rows_rest;
+    hipError_t e = hipSuccess;
     if (s->cs) {
         const int w = s->prec == P64 ? 2 : 4;  // values per vector chunk
-        if (!s->fixed && s->Nx % w == 0)
-            for (int t : {0, 256, 512, 1024}) cand.push_back({t, 8});
+        if (!s->fixed && s->Nx % w == 0) e = pick({0, 256, 512, 1024}, 0, &cs_threads);
     } else {
-        for (int r : {8, 4}) cand.push_back({0, r});
+        e = pick({8, 4}, 1, &rows1);
+        if (e == hipSuccess) e = pick({8, 4}, 2, &rows_rest);
     }
-    if (cand.size() < 2) return LB_OK;  // nothing to choose
-    float best = 0.0f;
-    std::pair<int, int> pick = cand[0];
-    for (const auto &c : cand) {
-        float ms = 0.0f;
-        hipError_t e = with_type(s, [&](auto *tag) {
-            using T = std::remove_pointer_t<decltype(tag)>;
-            return time_candidate<T>(s, c.first, c.second, reps, &ms);
-        });
-        if (e != hipSuccess) return fail(dev_status(e));
-        if (&c == &cand[0] || ms < best) {
-            best = ms;
-            pick = c;
-        }
-    }
+    if (e != hipSuccess) return fail(dev_status(e));
     drop_graphs(s);
-    s->cs_threads = pick.first;
-    s->fd_rows = pick.second;
+    s->cs_threads = cs_threads;
+    s->fd_rows = rows1;
+    s->fd_rows_rest = rows_rest;
     return LB_OK;
 }
 
-int lb_set_tuning(lb_sim *s, int cs_threads, int fd_rows)
+int lb_set_tuning(lb_sim *s, int cs_threads, int fd_rows, int fd_rows_rest)
 {
-    if (!s || cs_threads < 0 || cs_threads > 1024 || cs_threads % 64 || (fd_rows != 4 && fd_rows != 8))
+    auto rows_ok = [](int r) { return r == 4 || r == 8; };
+    if (!s || cs_threads < 0 || cs_threads > 1024 || cs_threads % 64 || !rows_ok(fd_rows) || !rows_ok(fd_rows_rest))
         return fail(LB_EINVAL);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
     drop_graphs(s);
     s->cs_threads = cs_threads;
     s->fd_rows = fd_rows;
+    s->fd_rows_rest = fd_rows_rest;
     return LB_OK;
 }
 
-int lb_get_tuning(const lb_sim *s, int *cs_threads, int *fd_rows)
+int lb_get_tuning(const lb_sim *s, int *cs_threads, int *fd_rows, int *fd_rows_rest)
 {
-    if (!s || !cs_threads || !fd_rows) return fail(LB_EINVAL);
+    if (!s || !cs_threads || !fd_rows || !fd_rows_rest) return fail(LB_EINVAL);
     *cs_threads = s->cs_threads;
     *fd_rows = s->fd_rows;
+    *fd_rows_rest = s->fd_rows_rest;
     return LB_OK;
 }
 

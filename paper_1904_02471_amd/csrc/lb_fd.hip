@@ -8,8 +8,19 @@ namespace lbm {
 
 namespace {
 
+// Waves per SIMD asked of the compiler: the periodic FP32 first-stage
+// kernels up to order 3 fit four in LDS and, held to 128 registers, without
+// spills; left alone the compiler takes a few more registers and drops to
+// three.  The later stages also stage the base state (more LDS) and stay at
+// three.
+template <typename T, int N, bool FIXED, bool WITH_GN>
+constexpr int fd_min_waves()
+{
+    return std::is_same<T, float>::value && !FIXED && !WITH_GN && N <= 3 ? 4 : 1;
+}
+
 template <typename T, int N, bool FIXED, bool DIAG, bool WITH_GN, int ROWS>
-__global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
+__global__ __launch_bounds__(kFdThreads, (fd_min_waves<T, N, FIXED, WITH_GN>())) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
                                                               const typename Arith<T>::type cb,
                                                               const Params<typename Arith<T>::type> p,
                                                               const DiagArgs<typename Arith<T>::type> d)

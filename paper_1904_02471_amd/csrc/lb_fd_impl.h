@@ -83,16 +83,19 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 //              beta2 = 13/12 (c-2d+e)^2 + 1/4 (3c-4d+e)^2
 //   weights    alpha_r = d_r / (eps + beta_r)^2, d = (0.1, 0.6, 0.3)
 //   value      sum alpha_r q_r / sum alpha_r.
-// Evaluated in terms of the second differences t_r and the first
-// differences cb = c - b, dc = d - c, with which
-//   q0 - c = t0/3 + cb/2,  q1 - c = (cb + 2 dc)/6,  q2 - c = dc/2 - t2/6,
-//   (a-4b+3c)/2 = t0/2 + cb,  (b-d)/2 = -(cb + dc)/2,  (3c-4d+e)/2 = t2/2 - dc,
+// Evaluated in terms of the second differences t_r, the first differences
+// cb = c - b, dc = d - c and their halves (exact), with which
+//   (a-4b+3c)/2 = t0/2 + cb = v0,  (b-d)/2 = -(cb/2 + dc/2) = -v1,
+//   (3c-4d+e)/2 = t2/2 - dc = v2,
+//   10 d_r (q_r - c) = t0/3 + cb/2,  cb + 2 dc,  3 dc/2 - t2/2 = dc/2 - v2,
 // and the weights over the common denominator (eps+beta0)^2 (eps+beta1)^2
-// (eps+beta2)^2 (one reciprocal per face).  On a sliding window the t_r,
-// eps + 13/12 t_r^2 and the first differences are common subexpressions of
-// neighbouring faces.  FP32 range: (eps + beta)^4 must stay a normal number,
-// hence the library accepts 1e-9 <= eps <= 1e9 for FP32 arithmetic.
-// Every multiply-add is an explicit fma (the library is compiled without
+// (eps+beta2)^2 (one reciprocal per face); numerator and denominator both
+// carry the factor 10 (10 d_r = 1, 6, 3), which leaves one instruction per
+// term.  On a sliding window the t_r, eps + 13/12 t_r^2, the first
+// differences and their halves are common subexpressions of neighbouring
+// faces.  FP32 range: (eps + beta)^4 must stay a normal number, hence the
+// library accepts 1e-9 <= eps <= 1e9 for FP32 arithmetic.  Every
+// multiply-add is an explicit fma (the library is compiled without
 // automatic contraction), so a face is the same function of its five inputs
 // wherever it is evaluated.
 template <typename CT>
@@ -103,17 +106,18 @@ __device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
     const CT t1 = fmaT(CT(-2), c, b + d);
     const CT t2 = fmaT(CT(-2), d, c + e);
     const CT cb = c - b, dc = d - c;
+    const CT hcb = h * cb, hdc = h * dc;
     const CT T0 = fmaT(k13 * t0, t0, eps), T1 = fmaT(k13 * t1, t1, eps), T2 = fmaT(k13 * t2, t2, eps);
-    const CT v0 = fmaT(h, t0, cb), v1 = h * (cb + dc), v2 = fmaT(h, t2, -dc);
+    const CT v0 = fmaT(h, t0, cb), v1 = hcb + hdc, v2 = fmaT(h, t2, -dc);
     const CT s0 = fmaT(v0, v0, T0), s1 = fmaT(v1, v1, T1), s2 = fmaT(v2, v2, T2);
     const CT S0 = s0 * s0, S1 = s1 * s1, S2 = s2 * s2;
     const CT A0 = S1 * S2, A1 = S0 * S2, A2 = S0 * S1;
-    // d_r (q_r - c)
-    const CT R0 = fmaT(CT(1.0 / 30.0), t0, CT(0.05) * cb);
-    const CT R1 = fmaT(CT(0.2), dc, CT(0.1) * cb);
-    const CT R2 = fmaT(CT(-0.05), t2, CT(0.15) * dc);
+    // 10 d_r (q_r - c)
+    const CT R0 = fmaT(CT(1.0 / 3.0), t0, hcb);
+    const CT R1 = fmaT(CT(2), dc, cb);
+    const CT R2 = hdc - v2;
     const CT num = fmaT(A0, R0, fmaT(A1, R1, A2 * R2));
-    const CT den = fmaT(CT(0.1), A0, fmaT(CT(0.6), A1, CT(0.3) * A2));
+    const CT den = fmaT(CT(6), A1, fmaT(CT(3), A2, A0));
     return fmaT(num, fast_rcp(den), c);
 }
 

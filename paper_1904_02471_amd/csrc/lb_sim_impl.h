@@ -52,9 +52,12 @@ struct lb_sim {
     int graph_steps = -1;             // -1: the model's default, 0: no graphs
     // Launch shapes of plain steps (set by lb_autotune / lb_set_tuning): CS
     // vector-row workgroup size (0: one chunk per thread), FD tile rows per
-    // thread (8: 64 x 32 tiles, 4: 64 x 16).  Results do not depend on them.
+    // thread (8: 64 x 32 tiles, 4: 64 x 16) of the first Runge-Kutta stage and
+    // of the later ones (which also read the step's base state).  Results do
+    // not depend on them.
     int cs_threads = 0;
     int fd_rows = 8;
+    int fd_rows_rest = 8;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;
 };

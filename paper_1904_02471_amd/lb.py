@@ -65,8 +65,9 @@ def _load():
         "lb_steps_done": (ctypes.c_longlong, [_vp]),
         "lb_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lb_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
-        "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
-        "lb_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "lb_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int)]),
         "lb_set_stream": (ctypes.c_int, [_vp, _vp]),
         "lb_synchronize": (ctypes.c_int, [_vp]),
         "lb_device_bytes": (ctypes.c_size_t, [_vp]),
@@ -217,13 +218,17 @@ class Sim:
         _check(_lib.lb_autotune(self._h, int(reps)), "lb_autotune")
         return self.tuning()
 
-    def set_tuning(self, cs_threads, fd_rows):
-        _check(_lib.lb_set_tuning(self._h, int(cs_threads), int(fd_rows)), "lb_set_tuning")
+    def set_tuning(self, cs_threads, fd_rows, fd_rows_rest=None):
+        """fd_rows: tile rows of the first FD stage, fd_rows_rest: of the
+        later stages (default: the same)."""
+        rest = fd_rows if fd_rows_rest is None else fd_rows_rest
+        _check(_lib.lb_set_tuning(self._h, int(cs_threads), int(fd_rows), int(rest)), "lb_set_tuning")
 
     def tuning(self):
-        a, b = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.lb_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)), "lb_get_tuning")
-        return a.value, b.value
+        """(cs_threads, fd_rows, fd_rows_rest) of the plain steps."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.lb_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "lb_get_tuning")
+        return a.value, b.value, c.value
 
     def set_stream(self, stream_handle):
         """stream_handle: an integer hipStream_t (e.g. torch.cuda.Stream().cuda_stream) or 0/None."""
@@ -309,8 +314,8 @@ def lb_autotune(sim, reps=20):
     return sim.autotune(reps)
 
 
-def lb_set_tuning(sim, cs_threads, fd_rows):
-    sim.set_tuning(cs_threads, fd_rows)
+def lb_set_tuning(sim, cs_threads, fd_rows, fd_rows_rest=None):
+    sim.set_tuning(cs_threads, fd_rows, fd_rows_rest)
 
 
 def lb_get_tuning(sim):

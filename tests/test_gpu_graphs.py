@@ -71,11 +71,11 @@ def test_graph_steps_argument_range():
 
 
 @pytest.mark.parametrize("model,Nx,Ny,prec,shapes", [
-    (lb.LB_CS_D2Q9, 256, 24, lb.LB_FP32, [(64, 8), (256, 8), (512, 8), (1024, 8)]),
-    (lb.LB_CS_D2Q9, 100, 10, lb.LB_FP64, [(128, 8)]),
-    (lb.LB_FD_D2Q16, 70, 40, lb.LB_FP32, [(0, 4)]),
-    (lb.LB_FD_D2Q36, 65, 33, lb.LB_FP64, [(0, 4)]),
-    (lb.LB_FD_D2Q16, 64, 48, lb.LB_FP16_SHIFTED, [(0, 4)]),
+    (lb.LB_CS_D2Q9, 256, 24, lb.LB_FP32, [(64, 8, 8), (256, 8, 8), (512, 8, 8), (1024, 8, 8)]),
+    (lb.LB_CS_D2Q9, 100, 10, lb.LB_FP64, [(128, 8, 8)]),
+    (lb.LB_FD_D2Q16, 70, 40, lb.LB_FP32, [(0, 4, 4), (0, 8, 4), (0, 4, 8)]),
+    (lb.LB_FD_D2Q36, 65, 33, lb.LB_FP64, [(0, 4, 4), (0, 8, 4)]),
+    (lb.LB_FD_D2Q16, 64, 48, lb.LB_FP16_SHIFTED, [(0, 4, 4), (0, 8, 4)]),
 ])
 def test_launch_shapes_do_not_change_results(model, Nx, Ny, prec, shapes):
     """Every tuned launch shape (CS workgroup size, FD tile height) gives
@@ -107,9 +107,9 @@ def test_launch_shapes_do_not_change_results(model, Nx, Ny, prec, shapes):
     g.set_probe(*workloads.separable_pattern("tgv", Nx, Ny))
     g.series_reserve(16)
     before = g.get_state()
-    cs_threads, fd_rows = g.autotune(3)
+    cs_threads, fd_rows, fd_rows_rest = g.autotune(3)
     assert np.array_equal(g.get_state(), before)
-    assert fd_rows in (4, 8) and cs_threads in (0, 256, 512, 1024)
+    assert fd_rows in (4, 8) and fd_rows_rest in (4, 8) and cs_threads in (0, 256, 512, 1024)
     g.step(9)
     g.step_sampled(23, 4)
     assert np.array_equal(g.get_state(), ref[0])
