@@ -12,7 +12,8 @@ Prints one JSON line: MLUPS of the whole step (node updates per second:
 one update advances a node by one CS step and one FD step), per-model MLUPS
 and HBM fractions, the roofline of the dominant kernel (the FD stage), the
 CS step at 4096^2 with FP32 and FP16-shifted storage (states larger than the
-last-level cache, so those byte rates are HBM rates), the serving stream,
+last-level cache, so those byte rates are HBM rates), the FD D2Q36 step at
+2048^2, the serving stream,
 and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
@@ -52,7 +53,8 @@ def parse():
     ap.add_argument("--sample-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cache-free", action="store_true",
-                    help="skip the 4096^2 CS FP32 / FP16 runs (state larger than the last-level cache)")
+                    help="skip the 4096^2 CS FP32 / FP16 runs (state larger than the last-level cache) "
+                         "and the 2048^2 FD D2Q36 run")
     ap.add_argument("--only", choices=["cs", "fd"], default=None,
                     help="time one model alone (profiling runs); the JSON line is then per model")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -112,6 +114,37 @@ def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
                      "bytes_per_node_step": 18 * s, "cs_threads": threads}
         sim.destroy()
     return out
+
+
+def fd_d2q36(lb, workloads, units, stream, n=2048, steps=20, warmup=3):
+    """FD D2Q36 (N = 4) plain steps on the n x n Taylor-Green vortex of the
+    D2Q36 workload (tau_FD = 5e-4, dt at CFL 0.5), FP32 storage, autotuned."""
+    import torch
+    ds = 1.0 / n
+    tau = 5e-4
+    vmax = lb.lb_model_info(lb.LB_FD_D2Q36)[0].max()
+    dt = units.fd_time_step(tau, ds, vmax, 0.5)
+    sim = lb.Sim(lb.LB_FD_D2Q36, n, n, tau, dt, ds, 4, precision=lb.LB_FP32)
+    sim.set_stream(stream.cuda_stream)
+    r, ux, uy, _ = workloads.taylor_green(n, n, 0.01, 1.0)
+    sim.init(r, ux, uy)
+    del r, ux, uy
+    shapes = sim.autotune(3)
+    sim.step(warmup)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        sim.step(steps)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    sim.destroy()
+    gbs = 8 * 36 * 4 * n * n / (ms * 1e-3) / 1e9
+    return {"grid": [n, n], "steps": steps, "tau_fd": tau, "dt_fd": dt, "ms_per_step": round(ms, 5),
+            "mlups": round(n * n / (ms * 1e-3) / 1e6, 1), "achieved_gbs_stagewise": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node_step": 8 * 36 * 4,
+            "fd_tile_rows": shapes[1], "fd_tile_rows_later_stages": shapes[2]}
 
 
 def source_digest(files):
@@ -381,6 +414,7 @@ def main():
         cs.destroy()
         fd.destroy()
         line["cs_d2q9_4096"] = cache_free_cs(lb, workloads, stream)
+        line["fd_d2q36"] = fd_d2q36(lb, workloads, units, stream)
     if args.serving_requests > 0:
         if args.only is not None or args.no_cache_free:
             cs.destroy()
