@@ -94,9 +94,11 @@ typedef struct lb_sim lb_sim;
  *   model_flags: lb_model | lb_precision.
  *   tau, dt, ds: relaxation time, time step, grid spacing (see conventions).
  *   N: order of the Hermite expansion of the equilibrium.
- * Validation: Nx, Ny >= 1 (FD: >= 3); CS needs N == 2 and tau > dt/2
- * (positive viscosity nu = c_s^2 (tau - dt/2), Section 2); FD needs
- * 1 <= N <= Q-1, the CFL bound and dt <= tau (Section 4.1).
+ * Validation: Nx, Ny >= 1, Nx * Ny <= 2^30 (periodic directions wrap, so
+ * one node per direction is a valid grid); CS needs N == 2 and
+ * tau > dt/2 (positive viscosity nu = c_s^2 (tau - dt/2), Section 2); FD
+ * needs 1 <= N <= Q-1, the CFL bound, dt <= tau (Section 4.1) and one
+ * population plane below 4 GiB (Nx * Ny * bytes per stored value < 2^32).
  * Allocates all device memory (2 state buffers for CS, 3 for FD) on the
  * current HIP device.  Returns NULL on error (see lb_last_error). */
 lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N);

@@ -373,6 +373,9 @@ int validate_create(int model_flags, int Nx, int Ny, double tau, double dt, doub
         return LB_OK;
     }
     if (N < 1 || N > mi.Q - 1) return LB_EINVAL;
+    // the stage kernels address a population plane with 32-bit byte offsets
+    const long long esize = precbits == LB_FP64 ? 8 : (precbits == LB_FP16_SHIFTED ? 2 : 4);
+    if ((long long)Nx * Ny * esize >= (1LL << 32)) return LB_EINVAL;
     // CFL = max |v_k,alpha| dt / ds <= 1 and dt < tau (Section 4.1); dt == tau
     // is accepted, as in the shear-wave runs of Section 4.2
     const double vmax = mi.xi[mi.Q - 1];

@@ -9,14 +9,13 @@ namespace lbm {
 namespace {
 
 // Waves per SIMD asked of the compiler: the periodic FP32 first-stage
-// kernels up to order 3 fit four in LDS and, held to 128 registers, without
-// spills; left alone the compiler takes a few more registers and drops to
-// three.  The later stages also stage the base state (more LDS) and stay at
-// three.
+// kernels up to order 4 fit four in LDS and, held to 128 registers, without
+// spills; left alone the compiler may take a few more registers and drop to
+// three.  The later stages also stage the base state (more LDS).
 template <typename T, int N, bool FIXED, bool WITH_GN>
 constexpr int fd_min_waves()
 {
-    return std::is_same<T, float>::value && !FIXED && !WITH_GN && N <= 3 ? 4 : 1;
+    return std::is_same<T, float>::value && !FIXED && !WITH_GN && N <= 4 ? 4 : 1;
 }
 
 template <typename T, int N, bool FIXED, bool DIAG, bool WITH_GN, int ROWS>

@@ -121,6 +121,57 @@ __device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
     return fmaT(num, fast_rcp(den), c);
 }
 
+// Plane access through a buffer resource: the plane's base address sits in
+// the (scalar) descriptor and every lane supplies a 32-bit byte offset, so
+// the per-population addressing needs no 64-bit vector arithmetic and no
+// per-lane 64-bit addresses held across the population loop.  Planes are
+// below 4 GiB (the library refuses larger finite-difference grids); the
+// descriptor's range is the plane's size, so an access past it would read
+// 0 or be dropped instead of touching other memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t fd_plane(const void *base, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
+}
+
+// Loads and stores of stored state values at a byte offset of a plane;
+// stores round as store_state does (stochastically to FP16 with r13).
+template <typename T>
+struct FdPlaneIO;
+template <>
+struct FdPlaneIO<float> {
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+    }
+};
+template <>
+struct FdPlaneIO<double> {
+    typedef unsigned int W __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, uint32_t)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, off, 0, 0);
+    }
+};
+template <>
+struct FdPlaneIO<__half> {
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t r13)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, half_sr(v, r13)), r, off, 0, 0);
+    }
+};
+
 __device__ __forceinline__ int fd_wrap(int v, int n)
 {
     int r = v % n;
@@ -246,11 +297,13 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     const int x0 = bx * kTX, y0 = by * kTY;
     const int Nx = p.Nx, Ny = p.Ny;
     const long long P = p.plane;
+    const uint32_t pbytes = (uint32_t)(P * (long long)sizeof(T));
+    using IO = FdPlaneIO<T>;
 
-    // --- offsets of the tile elements this thread stages (fixed over k) ---
-    // >= 0: element offset inside a plane; -1 / -2: left / right end state;
-    // -3: no element
-    int toff[kLoadsPerThread];
+    // --- byte offsets in a plane of the tile elements this thread stages
+    // (fixed over k); kLeftEnd / kRightEnd: the end states, kNoElem: none
+    constexpr uint32_t kNoElem = 0xffffffffu, kLeftEnd = 0xfffffffeu, kRightEnd = 0xfffffffdu;
+    uint32_t toff[kLoadsPerThread];
 #pragma unroll
     for (int i = 0; i < kLoadsPerThread; ++i) {
         const int e = tid + i * kFdThreads;
@@ -259,46 +312,46 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             const int gy = fd_wrap(y0 - kHalo + r, Ny);
             const int gxr = x0 - kHalo + c;
             if (FIXED && gxr < 0)
-                toff[i] = -1;
+                toff[i] = kLeftEnd;
             else if (FIXED && gxr >= Nx)
-                toff[i] = -2;
+                toff[i] = kRightEnd;
             else
-                toff[i] = gy * p.pitch + p.xoff + fd_wrap(gxr, Nx);
+                toff[i] = (uint32_t)(gy * p.pitch + p.xoff + fd_wrap(gxr, Nx)) * (uint32_t)sizeof(T);
         } else {
-            toff[i] = -3;
+            toff[i] = kNoElem;
         }
     }
     auto fetch = [&](int k, CT *reg) {
-        const T *sk = src + k * P;
+        const auto sk = fd_plane(src + k * P, pbytes);
 #pragma unroll
         for (int i = 0; i < kLoadsPerThread; ++i) {
-            const int o = toff[i];
-            if (o >= 0)
-                reg[i] = ld(sk + o);
-            else if (FIXED && o == -1)
+            const uint32_t o = toff[i];
+            if (o < kRightEnd)
+                reg[i] = IO::load(sk, o);
+            else if (FIXED && o == kLeftEnd)
                 reg[i] = p.ghost_l[k];
-            else if (FIXED && o == -2)
+            else if (FIXED && o == kRightEnd)
                 reg[i] = p.ghost_r[k];
         }
     };
     auto stash = [&](int buf, const CT *reg) {
 #pragma unroll
         for (int i = 0; i < kLoadsPerThread; ++i)
-            if (toff[i] != -3) tile[buf][tid + i * kFdThreads] = reg[i];
+            if (toff[i] != kNoElem) tile[buf][tid + i * kFdThreads] = reg[i];
     };
     // asynchronous copy of tile k into tile[buf]; complete after a wait on
     // the vector-memory counter
     auto fetch_lds = [&](int k, int buf) {
-        const T *sk = src + k * P;
+        const auto sk = fd_plane(src + k * P, pbytes);
         const int wave_base = tid & ~63;
 #pragma unroll
         for (int i = 0; i < kLoadsPerThread; ++i) {
-            const int o = toff[i];
-            if (o >= 0) {
-                __builtin_amdgcn_global_load_lds(sk + o, &tile[buf][i * kFdThreads + wave_base], 4, 0, 0);
-            } else if (FIXED && o == -1) {
+            const uint32_t o = toff[i];
+            if (o < kRightEnd) {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(sk, &tile[buf][i * kFdThreads + wave_base], 4, o, 0, 0, 0);
+            } else if (FIXED && o == kLeftEnd) {
                 tile[buf][tid + i * kFdThreads] = p.ghost_l[k];
-            } else if (FIXED && o == -2) {
+            } else if (FIXED && o == kRightEnd) {
                 tile[buf][tid + i * kFdThreads] = p.ghost_r[k];
             }
         }
@@ -309,9 +362,9 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     const int gy0 = y0 + wy * kRows;
     const bool colok = gx < Nx;
     const int noff0 = p.xoff + (colok ? gx : Nx - 1);
-    auto node_off = [&](int r) {
+    auto node_off = [&](int r) {  // byte offset inside a plane
         const int gy = gy0 + r;
-        return (gy < Ny ? gy : Ny - 1) * p.pitch + noff0;
+        return (uint32_t)((gy < Ny ? gy : Ny - 1) * p.pitch + noff0) * (uint32_t)sizeof(T);
     };
     auto active = [&](int r) { return colok && gy0 + r < Ny; };
 
@@ -328,10 +381,10 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 #pragma unroll 2
         for (int k = 0; k < p.K; ++k) {
             const CT vxk = p.vx[k], vyk = p.vy[k];
-            const T *sk = src + k * P;
+            const auto sk = fd_plane(src + k * P, pbytes);
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
-                const CT g = ld(sk + node_off(r));
+                const CT g = IO::load(sk, node_off(r));
                 drho[r] += g;
                 jx[r] = fmaT(g, vxk, jx[r]);
                 jy[r] = fmaT(g, vyk, jy[r]);
@@ -391,16 +444,16 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         CT gnv[kRows];
         if constexpr (kDma) {
             if (WITH_GN) {
-                const T *gk = gn + k * P;
+                const auto gk = fd_plane(gn + k * P, pbytes);
 #pragma unroll
                 for (int r = 0; r < kRows; ++r)
-                    __builtin_amdgcn_global_load_lds(gk + node_off(r), &gnl[(wy * kRows + r) * kTX], 4, 0, 0);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(gk, &gnl[(wy * kRows + r) * kTX], 4, node_off(r), 0, 0, 0);
             }
             if (k + 1 < p.K) fetch_lds(k + 1, buf ^ 1);
         } else if (WITH_GN) {
-            const T *gk = gn + k * P;
+            const auto gk = fd_plane(gn + k * P, pbytes);
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) gnv[r] = ld(gk + node_off(r));
+            for (int r = 0; r < kRows; ++r) gnv[r] = IO::load(gk, node_off(r));
         }
 
         // a. x-faces: faces xs*8 + 1 .. xs*8 + 8 of row xr (face i lies between
@@ -461,6 +514,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         __syncthreads();
 
         // c. node updates
+        const auto ok = fd_plane(out + k * P, pbytes);
         const int qi = p.ki[k], qj = p.kj[k];
         const CT wk = p.w[k];
         const CT vxs = vxk * p.inv_ds, vys = vyk * p.inv_ds;
@@ -494,7 +548,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 uint32_t rb = 0;
                 if constexpr (std::is_same<T, __half>::value)
                     rb = mix32((uint32_t)((gy0 + r) * Nx + gx), p.salt ^ ((uint32_t)k * 0x632be5abu));
-                store_state(out + k * P + node_off(r), res, rb >> 19);
+                IO::store(ok, node_off(r), res, rb >> 19);
             }
         }
 

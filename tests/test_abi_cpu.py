@@ -70,6 +70,8 @@ def test_d2q9_tables():
     ((lb.LB_FD_D2Q16 | lb.LB_IMEX, 8, 8, 1e-3, 0.05, 0.1, 3), lb.LB_ECFL),  # IMEX keeps the CFL bound
     ((lb.LB_FD_D2Q16 | (1 << 11), 8, 8, 1e-3, 1e-4, 0.1, 3), lb.LB_EINVAL),  # unknown flag
     ((7, 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),                # unknown model
+    ((lb.LB_FD_D2Q9 | lb.LB_FP64, 32768, 16384, 1.0, 1e-5, 1e-4, 2), lb.LB_EINVAL),  # FD plane of 4 GiB
+    ((lb.LB_FD_D2Q9, 32768, 32768, 1.0, 1e-5, 1e-4, 2), lb.LB_EINVAL),              # FD plane of 4 GiB
     ((lb.LB_CS_D2Q9 | (3 << 8), 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),
     ((lb.LB_CS_D2Q9, 8, 8, float("nan"), 1.0, 1.0, 2), lb.LB_EINVAL),
 ])
