@@ -28,10 +28,13 @@
 //      halo is staged in LDS (double-buffered; the next tile is prefetched
 //      into registers while the current one is used):
 //      a. x-faces: thread (row tid / 8, segment tid % 8) marches along its
-//         row over 8 faces from a 12-value register window; 32 lanes add the
-//         left face of column 0 of the 32 rows; faces go to LDS;
-//      b. y-faces: thread (lx, wy) marches up its column, 9 faces for its 8
-//         nodes, from a 13-value register window, in registers;
+//         row over 8 faces from a 12-value register window; 32 lanes of one
+//         wave (which one rotates with the tile) add the left face of
+//         column 0 of the 32 rows; faces go to LDS;
+//      b. y-faces: thread (lx, wy) marches up its column over the 8 faces
+//         above its 8 nodes, from a 12-value register window; the face
+//         below its first node is the top face of the thread below (LDS),
+//         the tile's bottom faces are computed by one wave;
 //      c. node update: flux differences, order-N equilibrium of population
 //         k, Runge-Kutta combination, store.
 //   The sign of v_kx / v_ky is uniform over the launch, so the upwind side
@@ -286,6 +289,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     constexpr int kLoadsPerThread = G::kLoadsPerThread, kSeg = G::kSeg;
     __shared__ CT tile[2][kTileElems];
     __shared__ CT xface[kTY * kXFaceStride];
+    __shared__ CT yface[(kFdThreads / kTX + 1) * kTX];  // y-faces below thread rows 0..3 and above row 3
     // FP32 storage: tiles and the Runge-Kutta base values are copied from
     // global memory straight into LDS (global_load_lds), without registers
     constexpr bool kDma = std::is_same<T, float>::value;
@@ -294,6 +298,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 
     const int tid = threadIdx.x;
     const int lx = tid & 63, wy = tid >> 6;
+    const int cw = diag_block & 3;  // wave of the column-0 x-faces
     const int x0 = bx * kTX, y0 = by * kTY;
     const int Nx = p.Nx, Ny = p.Ny;
     const long long P = p.plane;
@@ -457,7 +462,9 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         }
 
         // a. x-faces: faces xs*8 + 1 .. xs*8 + 8 of row xr (face i lies between
-        //    tile columns i-1 and i), marching; column-0 faces by 32 lanes
+        //    tile columns i-1 and i), marching; column-0 faces by kTY lanes of
+        //    wave cw (rotating with the tile, so that no SIMD takes them for
+        //    every workgroup)
         if (vxk != CT(0)) {
             CT w[kSeg + 4];
             CT *fx = &xface[xr * kXFaceStride + xs * kSeg + 1];
@@ -466,52 +473,69 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 2 + i];
 #pragma unroll
                 for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
-                if (tid < kTY) {
-                    const int b = (tid + kHalo) * kLX + kHalo - 1;  // upwind cell of the column-0 face
-                    xface[tid * kXFaceStride] = weno5(L[b - 2], L[b - 1], L[b], L[b + 1], L[b + 2], eps);
+                if (wy == cw && lx < kTY) {
+                    const int b = (lx + kHalo) * kLX + kHalo - 1;  // upwind cell of the column-0 face
+                    xface[lx * kXFaceStride] = weno5(L[b - 2], L[b - 1], L[b], L[b + 1], L[b + 2], eps);
                 }
             } else {
 #pragma unroll
                 for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 1 + i];
 #pragma unroll
                 for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
-                if (tid < kTY) {
-                    const int b = (tid + kHalo) * kLX + kHalo;  // upwind cell of the column-0 face
-                    xface[tid * kXFaceStride] = weno5(L[b + 2], L[b + 1], L[b], L[b - 1], L[b - 2], eps);
+                if (wy == cw && lx < kTY) {
+                    const int b = (lx + kHalo) * kLX + kHalo;  // upwind cell of the column-0 face
+                    xface[lx * kXFaceStride] = weno5(L[b + 2], L[b + 1], L[b], L[b - 1], L[b - 2], eps);
                 }
             }
         }
 
-        // b. y-faces: march up the column, 9 faces for the 8 nodes
+        // b. y-faces: march up the column over the faces above the thread's
+        //    nodes (face m lies below node m, m = 1 .. kRows); the face below
+        //    its first node is the top face of the thread below, passed in
+        //    LDS, and the tile's bottom faces come from wave cw
         CT dfy[kRows];
+        CT g1 = CT(0);  // face 1, paired with face 0 after the barrier
         if (vyk != CT(0)) {
-            CT w[kRows + 5];
+            CT w[kRows + 4];
             CT prev = CT(0);
+            const int c00 = kHalo * kLX + lx + kHalo;  // LDS cell of the column's tile row 0
             if (vyk > CT(0)) {
 #pragma unroll
-                for (int i = 0; i < kRows + 5; ++i) w[i] = L[c0 + (i - 3) * kLX];
+                for (int i = 0; i < kRows + 4; ++i) w[i] = L[c0 + (i - 2) * kLX];
 #pragma unroll
-                for (int m = 0; m <= kRows; ++m) {
-                    const CT G = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
-                    if (m > 0) dfy[m - 1] = G - prev;
+                for (int m = 1; m <= kRows; ++m) {
+                    const CT G = weno5(w[m - 1], w[m], w[m + 1], w[m + 2], w[m + 3], eps);
+                    if (m == 1)
+                        g1 = G;
+                    else
+                        dfy[m - 1] = G - prev;
                     prev = G;
                 }
+                if (wy == cw)
+                    yface[lx] = weno5(L[c00 - 3 * kLX], L[c00 - 2 * kLX], L[c00 - kLX], L[c00], L[c00 + kLX], eps);
             } else {
 #pragma unroll
-                for (int i = 0; i < kRows + 5; ++i) w[i] = L[c0 + (i - 2) * kLX];
+                for (int i = 0; i < kRows + 4; ++i) w[i] = L[c0 + (i - 1) * kLX];
 #pragma unroll
-                for (int m = 0; m <= kRows; ++m) {
-                    const CT G = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
-                    if (m > 0) dfy[m - 1] = G - prev;
+                for (int m = 1; m <= kRows; ++m) {
+                    const CT G = weno5(w[m + 3], w[m + 2], w[m + 1], w[m], w[m - 1], eps);
+                    if (m == 1)
+                        g1 = G;
+                    else
+                        dfy[m - 1] = G - prev;
                     prev = G;
                 }
+                if (wy == cw)
+                    yface[lx] = weno5(L[c00 + 2 * kLX], L[c00 + kLX], L[c00], L[c00 - kLX], L[c00 - 2 * kLX], eps);
             }
+            yface[(wy + 1) * kTX + lx] = prev;
         } else {
 #pragma unroll
             for (int r = 0; r < kRows; ++r) dfy[r] = CT(0);
         }
         if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
         __syncthreads();
+        if (vyk != CT(0)) dfy[0] = g1 - yface[wy * kTX + lx];
 
         // c. node updates
         const auto ok = fd_plane(out + k * P, pbytes);
