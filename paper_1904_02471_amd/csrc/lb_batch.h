@@ -24,7 +24,10 @@ struct BatchSlot {
 };
 
 // One workgroup of a batched launch: simulation `slot`, row (CS) or tile
-// (FD) `local`.
+// (FD) `local`.  FD tiles are 64 x 32 nodes in the first Runge-Kutta stage
+// (the canonical tiles of the fused diagnostics) and 64 x kFdLaterTileRows
+// in the later stages; a stage's output does not depend on the tile shape.
+constexpr int kFdLaterTileRows = 16;
 struct BatchWork {
     int slot, local;
 };

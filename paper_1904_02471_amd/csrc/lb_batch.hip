@@ -1,7 +1,7 @@
 // lb_batch.hip -- batched kernels of the serving form: one launch steps all
 // admitted simulations of a kind together, each workgroup taking one row
-// (collision-streaming) or one 64 x 32 tile (finite-difference) of one
-// simulation from a work list.  The per-row / per-tile device code is the
+// (collision-streaming) or one tile (finite-difference: 64 x 32 in the first
+// stage, 64 x 16 in the later ones) of one simulation from a work list.  The per-row / per-tile device code is the
 // same as in the single-simulation kernels (lb_cs_impl.h, lb_fd_impl.h).
 #include "lb_batch.h"
 #include "lb_cs_impl.h"
@@ -60,7 +60,9 @@ __global__ __launch_bounds__(kFdThreads) void fd_batch_kernel(const BatchSlot *_
         const DiagArgs<float> d{};
         const float *src = STAGE == 2 ? s.buf[1] : s.buf[2];
         float *out = STAGE == 2 ? s.buf[2] : s.buf[0];
-        fd_stage_tile<float, N, false, true>(src, s.buf[0], out, cb, s.p, d, bx, by, w.local, false);
+        static_assert(FdGeom<kFdLaterTileRows / 4>::kTY == kFdLaterTileRows, "later-stage tile height");
+        fd_stage_tile<float, N, false, true, kFdLaterTileRows / 4>(src, s.buf[0], out, cb, s.p, d, bx, by, w.local,
+                                                                   false);
     }
 }
 

@@ -78,10 +78,10 @@ struct DevArray {
     hipError_t ensure(size_t n)
     {
         if (n <= cap) return hipSuccess;
+        const size_t want = std::max(n, cap * 2);
         if (ptr) (void)hipFree(ptr);
         ptr = nullptr;
         cap = 0;
-        const size_t want = std::max(n, cap * 2);
         hipError_t e = hipMalloc(&ptr, want * sizeof(T));
         if (e == hipSuccess) cap = want;
         return e;
@@ -122,8 +122,11 @@ struct lb_server {
     int epoch = 0;
     DevArray<BatchSlot> d_slots;
     DevArray<BatchWork> d_cs;
-    std::map<int, DevArray<BatchWork>> d_fd;  // per equilibrium order
-    std::map<int, int> n_fd;
+    // FD work lists per equilibrium order: 64 x 32 tiles for the first
+    // Runge-Kutta stage (the canonical tiles of the fused diagnostics),
+    // 64 x 16 tiles for the later stages (more waves per SIMD)
+    std::map<int, DevArray<BatchWork>> d_fd, d_fd16;
+    std::map<int, int> n_fd, n_fd16;
     int n_cs = 0;
     DevArray<int> d_ids;
 
@@ -201,7 +204,7 @@ int lb_server::rebuild()
     const int n = (int)running.size();
     std::vector<BatchSlot> slots(n);
     std::vector<BatchWork> cs;
-    std::map<int, std::vector<BatchWork>> fd;
+    std::map<int, std::vector<BatchWork>> fd, fd16;
     std::vector<int> ids(n);
     for (int i = 0; i < n; ++i) {
         lb_sim *s = running[i].sim;
@@ -231,6 +234,9 @@ int lb_server::rebuild()
             const int tiles = fd_diag_blocks(s->Nx, s->Ny);
             auto &v = fd[s->N];
             for (int t = 0; t < tiles; ++t) v.push_back({i, t});
+            auto &v16 = fd16[s->N];
+            const int tiles16 = b.tiles_x * ((s->Ny + kFdLaterTileRows - 1) / kFdLaterTileRows);
+            for (int t = 0; t < tiles16; ++t) v16.push_back({i, t});
         }
     }
     hipError_t e = d_slots.ensure(std::max(n, 1));
@@ -242,16 +248,21 @@ int lb_server::rebuild()
     if (e == hipSuccess && !cs.empty())
         e = hipMemcpyAsync(d_cs.ptr, cs.data(), cs.size() * sizeof(BatchWork), hipMemcpyHostToDevice, stream);
     n_cs = (int)cs.size();
-    n_fd.clear();
-    for (auto &kv : fd) {
-        if (e != hipSuccess) break;
-        auto &arr = d_fd[kv.first];
-        e = arr.ensure(kv.second.size());
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(arr.ptr, kv.second.data(), kv.second.size() * sizeof(BatchWork), hipMemcpyHostToDevice,
-                               stream);
-        n_fd[kv.first] = (int)kv.second.size();
-    }
+    auto upload_lists = [&](std::map<int, std::vector<BatchWork>> &lists, std::map<int, DevArray<BatchWork>> &dev,
+                            std::map<int, int> &counts) {
+        counts.clear();
+        for (auto &kv : lists) {
+            if (e != hipSuccess) break;
+            auto &arr = dev[kv.first];
+            e = arr.ensure(kv.second.size());
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(arr.ptr, kv.second.data(), kv.second.size() * sizeof(BatchWork),
+                                   hipMemcpyHostToDevice, stream);
+            counts[kv.first] = (int)kv.second.size();
+        }
+    };
+    upload_lists(fd, d_fd, n_fd);
+    upload_lists(fd16, d_fd16, n_fd16);
     // the host vectors must outlive the copies
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     return dev_status(e);
@@ -267,8 +278,10 @@ int lb_server::run_chunk()
         const int E = epoch + i;
         e = launch_cs_batch(d_slots.ptr, d_cs.ptr, n_cs, E, stream);
         for (auto &kv : n_fd) {
-            for (int stage = 1; stage <= 3 && e == hipSuccess; ++stage)
-                e = launch_fd_batch(d_slots.ptr, d_fd[kv.first].ptr, kv.second, kv.first, stage, E, stream);
+            const int N = kv.first;
+            if (e == hipSuccess) e = launch_fd_batch(d_slots.ptr, d_fd[N].ptr, kv.second, N, 1, E, stream);
+            for (int stage = 2; stage <= 3 && e == hipSuccess; ++stage)
+                e = launch_fd_batch(d_slots.ptr, d_fd16[N].ptr, n_fd16[N], N, stage, E, stream);
         }
         if (e == hipSuccess) e = launch_finalize_batch(d_slots.ptr, d_ids.ptr, (int)running.size(), E, stream);
     }
@@ -477,6 +490,7 @@ void lb_server_destroy(lb_server *s)
     s->d_slots.release();
     s->d_cs.release();
     for (auto &kv : s->d_fd) kv.second.release();
+    for (auto &kv : s->d_fd16) kv.second.release();
     s->d_ids.release();
     for (lb_result &r : s->done) std::free(r.samples);
     if (s->stream) (void)hipStreamDestroy(s->stream);
