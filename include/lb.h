@@ -207,7 +207,8 @@ int lb_autotune(lb_sim *sim, int reps);
 /* Set the plain-step launch shapes directly: cs_threads 0 (one chunk per
  * thread) or a multiple of 64 up to 1024; fd_rows (first FD stage) and
  * fd_rows_rest (later FD stages, the last IMEX stage included) 8 (64 x 32
- * tiles) or 4 (64 x 16).  LB_EINVAL otherwise. */
+ * tiles) or 4 (64 x 16).  LB_EINVAL otherwise.  Defaults of a new handle:
+ * 0, 8, 4. */
 int lb_set_tuning(lb_sim *sim, int cs_threads, int fd_rows, int fd_rows_rest);
 
 /* The current plain-step launch shapes (host ints). */

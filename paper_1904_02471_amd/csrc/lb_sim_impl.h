@@ -57,7 +57,7 @@ struct lb_sim {
     // not depend on them.
     int cs_threads = 0;
     int fd_rows = 8;
-    int fd_rows_rest = 8;
+    int fd_rows_rest = 4;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;
 };
