@@ -283,8 +283,10 @@ def serving_bench(n_requests, every):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the hot path here is one simulation per GPU; "
-              "see the sharding notes in DESIGN.md. Requested --gpus %d." % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only: a simulation runs on one GPU (served simulations are "
+              "independent, one server per GPU; a single large grid would need y-slab sharding with halo "
+              "exchanges, which this library does not implement). Requested --gpus %d." % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
