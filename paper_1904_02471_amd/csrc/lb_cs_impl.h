@@ -99,16 +99,24 @@ __device__ __forceinline__ CsMoments<CT> cs_collide(const CT (&g)[9], CT (&o)[9]
     return m;
 }
 
-// Diagnostics of one node (input state of the step).
+// Diagnostics of one node (input state of the step); qx, qy: the probe
+// pattern at the node, ax[x] ay[y] and bx[x] by[y].
 template <typename CT>
-__device__ __forceinline__ void cs_diag_node(DiagAcc &acc, const CsMoments<CT> &m, const DiagArgs<CT> &d, int x,
-                                             CT pay, CT pby)
+__device__ __forceinline__ void cs_diag_node_q(DiagAcc &acc, const CsMoments<CT> &m, bool probe, CT qx, CT qy)
 {
     acc.v[0] += (double)m.drho;
     acc.v[1] += (double)m.jx;
     acc.v[2] += (double)m.jy;
     acc.v[3] += (double)(CT(0.5) * m.rho * (m.ux * m.ux + m.uy * m.uy));
-    if (d.ax) acc.v[4] += (double)(m.ux * (d.ax[x] * pay) + m.uy * (d.bx[x] * pby));
+    if (probe) acc.v[4] += (double)(m.ux * qx + m.uy * qy);
+}
+
+template <typename CT>
+__device__ __forceinline__ void cs_diag_node(DiagAcc &acc, const CsMoments<CT> &m, const DiagArgs<CT> &d, int x,
+                                             CT pay, CT pby)
+{
+    const bool probe = d.ax != nullptr;
+    cs_diag_node_q(acc, m, probe, probe ? d.ax[x] * pay : CT(0), probe ? d.bx[x] * pby : CT(0));
 }
 
 // Random bits of the stochastic FP16 rounding: 13 per population, from one
@@ -320,6 +328,17 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
         in[6].load(rs + 6 * P + x);
         in[7].load(rn + 7 * P + x);
         in[8].load(rn + 8 * P + x);
+        // the probe pattern of the chunk's nodes, loaded with the chunk
+        CT qx[W], qy[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) qx[j] = qy[j] = CT(0);
+        if (DIAG && d.ax) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                qx[j] = d.ax[x + j] * pay;
+                qy[j] = d.bx[x + j] * pby;
+            }
+        }
         // neighbours across the chunk edges (lanes of one wave hold
         // consecutive chunks of the row)
         T l1 = in[1].prev_lane_last(), l5 = in[5].prev_lane_last(), l8 = in[8].prev_lane_last();
@@ -365,7 +384,7 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
                     out[k].set(j, o[k]);
                 }
             }
-            if (DIAG) cs_diag_node(acc, m, d, x + j, pay, pby);
+            if (DIAG) cs_diag_node_q(acc, m, d.ax != nullptr, qx[j], qy[j]);
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[k].store(orow + k * P + x);
