@@ -193,6 +193,13 @@ long long lb_steps_done(const lb_sim *sim);
  * outside [-1, 4096]. */
 int lb_set_graph_steps(lb_sim *sim, int steps);
 
+/* FP16 storage: the stream of counter-based random bits that the stochastic
+ * rounding draws (seed 0 by default).  Different seeds give independent
+ * realisations of the rounding; FP32 and FP64 storage ignore it.  The bits
+ * are a function of (seed, step, node, population, stage), so a run repeats
+ * exactly for a given seed. */
+int lb_set_rounding_seed(lb_sim *sim, unsigned seed);
+
 /* Autotuning of the launch shapes of plain steps (steps without sampling;
  * results are bitwise the same for every shape).  Times `reps` launches of
  * each candidate on the handle's own buffers, leaving the state unchanged,

@@ -108,7 +108,7 @@ Params<CT> make_params(const lb_sim *s)
     p.inv_ds = (CT)(1.0 / s->ds);
     p.inv_tau = (CT)(1.0 / s->tau);
     p.eps = (CT)s->eps;
-    p.salt = mix_host((unsigned)s->steps);
+    p.salt = mix_host((unsigned)s->steps ^ (s->rounding_seed * 0x9e3779b1u));
     for (int k = 0; k < s->K; ++k) {
         p.w[k] = (CT)s->mi.w[k];
         p.vx[k] = (CT)s->mi.vx[k];
@@ -822,6 +822,15 @@ int lb_get_tuning(const lb_sim *s, int *cs_threads, int *fd_rows, int *fd_rows_r
     *cs_threads = s->cs_threads;
     *fd_rows = s->fd_rows;
     *fd_rows_rest = s->fd_rows_rest;
+    return LB_OK;
+}
+
+int lb_set_rounding_seed(lb_sim *s, unsigned seed)
+{
+    if (!s) return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
+    s->rounding_seed = seed;
     return LB_OK;
 }
 

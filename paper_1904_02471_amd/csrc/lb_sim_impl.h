@@ -50,6 +50,7 @@ struct lb_sim {
     // Runs of plain steps replay a captured graph of graph_len steps (CS: one
     // per starting buffer; FD: [0]); dropped whenever the parameters change.
     int graph_steps = -1;             // -1: the model's default, 0: no graphs
+    unsigned rounding_seed = 0;       // FP16 stochastic rounding: random-bit stream
     // Launch shapes of plain steps (set by lb_autotune / lb_set_tuning): CS
     // vector-row workgroup size (0: one chunk per thread), FD tile rows per
     // thread (8: 64 x 32 tiles, 4: 64 x 16) of the first Runge-Kutta stage and

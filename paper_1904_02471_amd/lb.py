@@ -22,7 +22,7 @@ Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_F
 EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
            "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
-           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_autotune", "lb_set_tuning",
+           "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_rounding_seed", "lb_autotune", "lb_set_tuning",
            "lb_get_tuning", "lb_set_stream", "lb_synchronize",
            "lb_device_bytes",
            "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
@@ -64,6 +64,7 @@ def _load():
         "lb_set_state": (ctypes.c_int, [_vp, _dp]),
         "lb_steps_done": (ctypes.c_longlong, [_vp]),
         "lb_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_set_rounding_seed": (ctypes.c_int, [_vp, ctypes.c_uint]),
         "lb_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "lb_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -213,6 +214,10 @@ class Sim:
         """Steps per replayed HIP graph for runs of plain steps (-1: default, 0: off)."""
         _check(_lib.lb_set_graph_steps(self._h, int(steps)), "lb_set_graph_steps")
 
+    def set_rounding_seed(self, seed):
+        """FP16 storage: the random-bit stream of the stochastic rounding (0 by default)."""
+        _check(_lib.lb_set_rounding_seed(self._h, int(seed)), "lb_set_rounding_seed")
+
     def autotune(self, reps=20):
         """Time the plain-step launch shapes on this simulation and keep the fastest."""
         _check(_lib.lb_autotune(self._h, int(reps)), "lb_autotune")
@@ -308,6 +313,10 @@ def lb_steps_done(sim):
 
 def lb_set_graph_steps(sim, steps):
     sim.set_graph_steps(steps)
+
+
+def lb_set_rounding_seed(sim, seed):
+    sim.set_rounding_seed(seed)
 
 
 def lb_autotune(sim, reps=20):

@@ -124,12 +124,14 @@ def test_taylor_green_512_fp32_vs_fp64(model):
     assert nu_fit == pytest.approx(nu, rel=1e-3)
 
 
-def tgv4096_nu(prec):
+def tgv4096_nu(prec, seed=0):
     """TGV 4096^2 CS D2Q9 tau = 0.55, u0 = 0.01, 5000 steps: viscosity fitted
-    with the acoustic modulation from FP64 reductions of the projection."""
+    with the acoustic modulation from FP64 reductions of the projection
+    (seed: the random-bit stream of FP16 stochastic rounding)."""
     n = 4096
     k = 2 * math.pi / n
     g, dt, nu, _ = tgv_pair(lb.LB_CS_D2Q9, n, prec, tau_std=0.55)
+    g.set_rounding_seed(seed)
     rows = g.run_sampled(5000, 10)
     del g
     t = np.arange(0, 5001, 10, dtype=float)
@@ -144,18 +146,26 @@ def test_taylor_green_4096_fp32():
 
 
 def test_taylor_green_4096_fp16():
-    """FP16-shifted storage with stochastic rounding.  The vortex decays by
-    4e-4 over the run, ~8e-8 per step, while one FP16 ulp of the stored
-    populations is ~5e-4 of them: round-to-nearest freezes the state between
-    ulps (fitted nu 15% off).  Stochastic rounding is unbiased, and what is
-    left is its noise: ~1e-6 of momentum per node and step, which projects
-    onto the vortex as a random walk whose least-squares slope error is of
-    order 1e-3 of the decay rate over 5000 steps (1.1e-3 measured).  Bound:
-    5e-3 (the FP32 storage case above meets 1e-3)."""
-    print("case: tgv 4096 fp16", flush=True)
-    nu_fit, nu = tgv4096_nu(lb.LB_FP16_SHIFTED)
-    print("nu fp16 %.7f analytic %.7f" % (nu_fit, nu), flush=True)
-    assert nu_fit == pytest.approx(nu, rel=5e-3)
+    """FP16-shifted storage with stochastic rounding, six independent
+    realisations of the rounding (seeds 0-5).  The vortex decays by 4e-4 over
+    the run, ~8e-8 per step, while one FP16 ulp of the stored populations is
+    ~5e-4 of them: round-to-nearest freezes the state between ulps (fitted nu
+    15% off, the same every run).  Stochastic rounding is unbiased, and what
+    is left is its noise: ~1e-6 of momentum per node and step, which the
+    vortex integrates as a random walk; over 5000 steps the fitted nu of one
+    run scatters by ~7e-3 (relative standard deviation over 8 seeds).  Bounds:
+    the mean over the six runs within 1e-2 (3.7 standard errors) and every run
+    within 3e-2 (4.5 standard deviations); the FP32 storage case above meets
+    1e-3 in one run."""
+    errs = []
+    for seed in range(6):
+        print("case: tgv 4096 fp16 seed", seed, flush=True)
+        nu_fit, nu = tgv4096_nu(lb.LB_FP16_SHIFTED, seed)
+        errs.append(nu_fit / nu - 1)
+        print("nu fp16 seed %d: %.7f analytic %.7f (rel %+.2e)" % (seed, nu_fit, nu, errs[-1]), flush=True)
+    print("mean rel error %+.2e, std %.2e" % (np.mean(errs), np.std(errs, ddof=1)), flush=True)
+    assert abs(np.mean(errs)) < 1e-2
+    assert max(abs(e) for e in errs) < 3e-2
 
 
 def test_taylor_green_2048_fd_d2q36():
