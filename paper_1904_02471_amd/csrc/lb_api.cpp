@@ -143,6 +143,9 @@ int alloc_buffers(lb_sim *s)
     s->pitch = s->Nx + 2 * s->xoff;
     s->plane = (long long)s->pitch * s->Ny;
     s->buf_bytes = (size_t)s->K * (size_t)s->plane * s->esize;
+    if (!s->cs)  // the moment planes (fd_mom_offset), in the arithmetic type
+        s->buf_bytes = (size_t)fd_mom_offset(s->K, s->plane, s->esize) +
+                       3 * (size_t)s->plane * (s->prec == P64 ? sizeof(double) : sizeof(float));
     for (int i = 0; i < s->nbuf; ++i) {
         if (hipMalloc(&s->buf[i], s->buf_bytes) != hipSuccess) {
             (void)hipGetLastError();
@@ -373,8 +376,9 @@ int validate_create(int model_flags, int Nx, int Ny, double tau, double dt, doub
         return LB_OK;
     }
     if (N < 1 || N > mi.Q - 1) return LB_EINVAL;
-    // the stage kernels address a population plane with 32-bit byte offsets
-    const long long esize = precbits == LB_FP64 ? 8 : (precbits == LB_FP16_SHIFTED ? 2 : 4);
+    // the stage kernels address a population plane, and a moment plane in the
+    // arithmetic type (at least 4 bytes a value), with 32-bit byte offsets
+    const long long esize = precbits == LB_FP64 ? 8 : 4;
     if ((long long)Nx * Ny * esize >= (1LL << 32)) return LB_EINVAL;
     // CFL = max |v_k,alpha| dt / ds <= 1 and dt < tau (Section 4.1); dt == tau
     // is accepted, as in the shear-wave runs of Section 4.2
@@ -612,7 +616,10 @@ int lb_init(lb_sim *s, const double *rho, const double *ux, const double *uy)
         const Params<double> p = make_params<double>(s);
         hipError_t e = with_type(s, [&](auto *tag) {
             using T = std::remove_pointer_t<decltype(tag)>;
-            return launch_init<T>(bufp<T>(s, 0), d, d + n, d + 2 * n, s->cs, p, s->stream);
+            hipError_t e = launch_init<T>(bufp<T>(s, 0), d, d + n, d + 2 * n, s->cs, p, s->stream);
+            if (e == hipSuccess && !s->cs)
+                e = launch_fd_moments<T>(bufp<T>(s, 0), make_params<typename Arith<T>::type>(s), s->stream);
+            return e;
         });
         rc = dev_status(e);
         if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
@@ -645,7 +652,10 @@ int lb_set_state(lb_sim *s, const double *f)
         const Params<double> p = make_params<double>(s);
         hipError_t e = with_type(s, [&](auto *tag) {
             using T = std::remove_pointer_t<decltype(tag)>;
-            return launch_set_state<T>(bufp<T>(s, 0), d, s->cs, p, s->stream);
+            hipError_t e = launch_set_state<T>(bufp<T>(s, 0), d, s->cs, p, s->stream);
+            if (e == hipSuccess && !s->cs)
+                e = launch_fd_moments<T>(bufp<T>(s, 0), make_params<typename Arith<T>::type>(s), s->stream);
+            return e;
         });
         rc = dev_status(e);
         if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;

@@ -8,18 +8,12 @@ namespace lbm {
 
 namespace {
 
-// Waves per SIMD asked of the compiler: the periodic FP32 first-stage
-// kernels up to order 4 fit four in LDS and, held to 128 registers, without
-// spills; left alone the compiler may take a few more registers and drop to
-// three.  The later stages also stage the base state (more LDS).
-template <typename T, int N, bool FIXED, bool WITH_GN>
-constexpr int fd_min_waves()
-{
-    return std::is_same<T, float>::value && !FIXED && !WITH_GN && N <= 4 ? 4 : 1;
-}
-
+// No occupancy is asked of the compiler: with the moments of the output
+// accumulated in registers, holding the 64 x 32 first-stage kernels to 128
+// registers (four waves per SIMD) spills, and three waves without spills
+// run faster.
 template <typename T, int N, bool FIXED, bool DIAG, bool WITH_GN, int ROWS>
-__global__ __launch_bounds__(kFdThreads, (fd_min_waves<T, N, FIXED, WITH_GN>())) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
+__global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
                                                               const typename Arith<T>::type cb,
                                                               const Params<typename Arith<T>::type> p,
                                                               const DiagArgs<typename Arith<T>::type> d)
@@ -31,7 +25,43 @@ __global__ __launch_bounds__(kFdThreads, (fd_min_waves<T, N, FIXED, WITH_GN>()))
     const int b = blockIdx.x, q = nb / 8, r = nb % 8, x = b % 8;
     const int tile = x * q + (x < r ? x : r) + b / 8;
     const int tiles_x = (p.Nx + kTX - 1) / kTX;
-    fd_stage_tile<T, N, FIXED, WITH_GN, ROWS>(src, gn, out, cb, p, d, tile % tiles_x, tile / tiles_x, tile, DIAG);
+    fd_stage_tile<T, N, FIXED, WITH_GN, ROWS, true>(src, gn, out, cb, p, d, tile % tiles_x, tile / tiles_x, tile,
+                                                    DIAG);
+}
+
+// Moments of a stored value v of population k, accumulated in ascending k
+// (the order and operations of the moment planes, fd_mom_offset).
+template <typename CT>
+struct MomAcc {
+    CT drho = CT(0), jx = CT(0), jy = CT(0);
+    __device__ __forceinline__ void add(const Params<CT> &p, int k, CT v)
+    {
+        drho += v;
+        jx = fmaT(v, p.vx[k], jx);
+        jy = fmaT(v, p.vy[k], jy);
+    }
+    // into the moment planes of the state buffer `buf`, at element index o
+    template <typename T>
+    __device__ __forceinline__ void store(const Params<CT> &p, T *buf, long long o) const
+    {
+        CT *m = reinterpret_cast<CT *>(reinterpret_cast<char *>(buf) + fd_mom_offset(p.K, p.plane, (int)sizeof(T)));
+        m[o] = drho;
+        m[p.plane + o] = jx;
+        m[2 * p.plane + o] = jy;
+    }
+};
+
+// Moment planes of g from its populations (one thread per node).
+template <typename T>
+__global__ __launch_bounds__(256) void fd_moments_kernel(T *g, const Params<typename Arith<T>::type> p)
+{
+    using CT = typename Arith<T>::type;
+    const long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (node >= (long long)p.Nx * p.Ny) return;
+    const long long o = (node / p.Nx) * p.pitch + p.xoff + node % p.Nx;
+    MomAcc<CT> m;
+    for (int k = 0; k < p.K; ++k) m.add(p, k, ld(g + k * p.plane + o));
+    m.store(p, g, o);
 }
 
 // ---------------------------------------------------------------------
@@ -80,7 +110,7 @@ __device__ __forceinline__ CT node_geq(const Params<CT> &p, const NodeEq<CT, N> 
     return fd_geq<CT, N>(p.w[k], hx, hy, p.rho0, q.drho, q.ux, q.uy, q.dlt);
 }
 
-// First stage: out = relaxed g (one thread per node).
+// First stage: out = relaxed g (one thread per node), with its moment planes.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void fd_imex_relax_kernel(const T *__restrict__ g, T *__restrict__ out,
                                                             const Params<typename Arith<T>::type> p,
@@ -94,18 +124,21 @@ __global__ __launch_bounds__(256) void fd_imex_relax_kernel(const T *__restrict_
     const long long P = p.plane;
     const NodeEq<CT, N> q = node_eq<CT, N>(p, [&](int k) { return ld(g + k * P + o); });
     uint32_t rb = mix32((uint32_t)node, p.salt);
+    MomAcc<CT> m;
     for (int k = 0; k < p.K; ++k) {
         const CT h = ld(g + k * P + o);
         rb = xorshift32(rb);
-        store_state(out + k * P + o, fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa, rb >> 19);
+        m.add(p, k, store_state(out + k * P + o, fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa, rb >> 19));
     }
+    m.store(p, out, o);
 }
 
 // Second stage, from y = f1 + dt L(f1) (in yb), f = g^n (in g) and f1 (in
 // f1b): the explicit part h = f + dt A(f1) + (1 - 2g) dt R(f1) is
 // y + 3 (f - f1) (as g dt R(f1) = f1 - f); writes f2 = relax(h) over yb and
 // b = 2 f1 + h - f - f2 over f1b, so that the last stage
-// f' = b + (f2 + dt L(f2) - b) / 2 equals f + dt/2 [L(f1) + L(f2)].
+// f' = b + (f2 + dt L(f2) - b) / 2 equals f + dt/2 [L(f1) + L(f2)].  The
+// moment planes of yb are f2's.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void fd_imex_mid_kernel(T *__restrict__ yb, const T *__restrict__ g,
                                                           T *__restrict__ f1b,
@@ -124,16 +157,18 @@ __global__ __launch_bounds__(256) void fd_imex_mid_kernel(T *__restrict__ yb, co
     };
     const NodeEq<CT, N> q = node_eq<CT, N>(p, hk);
     uint32_t rb = mix32((uint32_t)node, p.salt);
+    MomAcc<CT> m;
     for (int k = 0; k < p.K; ++k) {
         const CT f1 = ld(f1b + k * P + o), f = ld(g + k * P + o);
         const CT h = fmaT(CT(3), f - f1, ld(yb + k * P + o));
         const CT f2 = fmaT(a, node_geq<CT, N>(p, q, k), h) * inv1pa;
         const CT b = fmaT(CT(2), f1, h - f) - f2;
         rb = xorshift32(rb);
-        store_state(yb + k * P + o, f2, rb >> 19);
+        m.add(p, k, store_state(yb + k * P + o, f2, rb >> 19));
         rb = xorshift32(rb);
         store_state(f1b + k * P + o, b, rb >> 19);
     }
+    m.store(p, yb, o);
 }
 
 template <typename T, int N, bool FIXED, int ROWS>
@@ -228,6 +263,18 @@ template hipError_t launch_fd_imex<__half>(int, __half *, const __half *, __half
                                            hipStream_t);
 template hipError_t launch_fd_imex<double>(int, double *, const double *, double *, const Params<double> &, double,
                                            hipStream_t);
+
+template <typename T>
+hipError_t launch_fd_moments(T *g, const Params<typename Arith<T>::type> &p, hipStream_t s)
+{
+    const long long nodes = (long long)p.Nx * p.Ny;
+    hipLaunchKernelGGL((fd_moments_kernel<T>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s, g, p);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fd_moments<float>(float *, const Params<float> &, hipStream_t);
+template hipError_t launch_fd_moments<__half>(__half *, const Params<float> &, hipStream_t);
+template hipError_t launch_fd_moments<double>(double *, const Params<double> &, hipStream_t);
 
 int fd_diag_blocks(int Nx, int Ny)
 {

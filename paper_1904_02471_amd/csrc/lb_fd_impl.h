@@ -22,8 +22,9 @@
 //   column lx and the 8 rows 8 wy .. 8 wy + 7 (the canonical geometry; the
 //   tile height is a template parameter, 64 x 16 with 4 rows per thread is
 //   the other choice of the autotuner, with 4-face x segments).
-//   1. moments: the thread gathers the K values of its 8 nodes and keeps
-//      drho, u_x, u_y per node.
+//   1. moments: the thread reads drho, j_x, j_y of its 8 nodes from the
+//      input's moment planes (the batched kernels sum them from the K
+//      populations instead: the same values) and keeps drho, u_x, u_y.
 //   2. loop over the populations k; the tile of population k with a 3-node
 //      halo is staged in LDS (double-buffered; the next tile is prefetched
 //      into registers while the current one is used):
@@ -36,7 +37,8 @@
 //         below its first node is the top face of the thread below (LDS),
 //         the tile's bottom faces are computed by one wave;
 //      c. node update: flux differences, order-N equilibrium of population
-//         k, Runge-Kutta combination, store.
+//         k, Runge-Kutta combination, store; the stored values are summed
+//         into the output's moments, written after the last population.
 //   The sign of v_kx / v_ky is uniform over the launch, so the upwind side
 //   is a scalar branch and every LDS access has a constant offset.
 #pragma once
@@ -137,7 +139,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t fd_plane(const void *base, uin
 }
 
 // Loads and stores of stored state values at a byte offset of a plane;
-// stores round as store_state does (stochastically to FP16 with r13).
+// stores round as store_state does (stochastically to FP16 with r13) and
+// return the value stored.
 template <typename T>
 struct FdPlaneIO;
 template <>
@@ -146,10 +149,14 @@ struct FdPlaneIO<float> {
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     }
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t)
+    static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t)
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+        return v;
     }
+    static __device__ __forceinline__ float pack(float v, uint32_t) { return v; }
+    static __device__ __forceinline__ float unpack(float b) { return b; }
+    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, float b) { store(r, off, b, 0); }
 };
 template <>
 struct FdPlaneIO<double> {
@@ -158,10 +165,14 @@ struct FdPlaneIO<double> {
     {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
     }
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, uint32_t)
+    static __device__ __forceinline__ double store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, uint32_t)
     {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, off, 0, 0);
+        return v;
     }
+    static __device__ __forceinline__ double pack(double v, uint32_t) { return v; }
+    static __device__ __forceinline__ double unpack(double b) { return b; }
+    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, double b) { store(r, off, b, 0); }
 };
 template <>
 struct FdPlaneIO<__half> {
@@ -169,9 +180,19 @@ struct FdPlaneIO<__half> {
     {
         return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
     }
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t r13)
+    static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t r13)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, half_sr(v, r13)), r, off, 0, 0);
+        const __half h = half_sr(v, r13);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, off, 0, 0);
+        return __half2float(h);
+    }
+    // the stored bits of v (rounded stochastically with r13), their value,
+    // and their store
+    static __device__ __forceinline__ __half pack(float v, uint32_t r13) { return half_sr(v, r13); }
+    static __device__ __forceinline__ float unpack(__half b) { return __half2float(b); }
+    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, __half b)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, b), r, off, 0, 0);
     }
 };
 
@@ -275,8 +296,10 @@ __device__ __forceinline__ CT fd_geq(CT wk, const CT (&hx)[N + 1], const CT (&hy
 // workgroup; with `diag` the diagnostics of the tile's input state go to
 // partial[diag_block].  Every face and node is evaluated by the same
 // sequence of operations for any ROWS, so the stage output does not depend
-// on the tile height.
-template <typename T, int N, bool FIXED, bool WITH_GN, int ROWS = kFdRows>
+// on the tile height.  MOM: the moments of the input come from its moment
+// planes (fd_mom_offset), and the stage writes those of its output; without
+// it the moments are summed from the input's populations (the same values).
+template <typename T, int N, bool FIXED, bool WITH_GN, int ROWS = kFdRows, bool MOM = false>
 __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T *gn, T *out,
                                               const typename Arith<T>::type cb,
                                               const Params<typename Arith<T>::type> &p,
@@ -367,10 +390,14 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     const int gy0 = y0 + wy * kRows;
     const bool colok = gx < Nx;
     const int noff0 = p.xoff + (colok ? gx : Nx - 1);
-    auto node_off = [&](int r) {  // byte offset inside a plane
+    auto node_idx = [&](int r) {  // element index inside a plane
         const int gy = gy0 + r;
-        return (uint32_t)((gy < Ny ? gy : Ny - 1) * p.pitch + noff0) * (uint32_t)sizeof(T);
+        return (uint32_t)((gy < Ny ? gy : Ny - 1) * p.pitch + noff0);
     };
+    auto node_off = [&](int r) { return node_idx(r) * (uint32_t)sizeof(T); };  // byte offset
+    using MIO = FdPlaneIO<CT>;
+    const uint32_t mbytes = (uint32_t)(P * (long long)sizeof(CT));  // one moment plane
+    const unsigned long long moff = fd_mom_offset(p.K, P, (int)sizeof(T));
     auto active = [&](int r) { return colok && gy0 + r < Ny; };
 
     CT pre[kLoadsPerThread];
@@ -381,18 +408,31 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     CT drho[kRows], uxv[kRows], uyv[kRows];
     {
         CT jx[kRows], jy[kRows];
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) drho[r] = jx[r] = jy[r] = CT(0);
-#pragma unroll 2
-        for (int k = 0; k < p.K; ++k) {
-            const CT vxk = p.vx[k], vyk = p.vy[k];
-            const auto sk = fd_plane(src + k * P, pbytes);
+        if constexpr (MOM) {
+            const char *mb = reinterpret_cast<const char *>(src) + moff;
+            const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
+                       m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
-                const CT g = IO::load(sk, node_off(r));
-                drho[r] += g;
-                jx[r] = fmaT(g, vxk, jx[r]);
-                jy[r] = fmaT(g, vyk, jy[r]);
+                const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
+                drho[r] = MIO::load(m0, o);
+                jx[r] = MIO::load(m1, o);
+                jy[r] = MIO::load(m2, o);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) drho[r] = jx[r] = jy[r] = CT(0);
+#pragma unroll 2
+            for (int k = 0; k < p.K; ++k) {
+                const CT vxk = p.vx[k], vyk = p.vy[k];
+                const auto sk = fd_plane(src + k * P, pbytes);
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const CT g = IO::load(sk, node_off(r));
+                    drho[r] += g;
+                    jx[r] = fmaT(g, vxk, jx[r]);
+                    jy[r] = fmaT(g, vyk, jy[r]);
+                }
             }
         }
         DiagAcc acc;
@@ -436,6 +476,13 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         if (p.K > 1) fetch(1, pre);
     }
     __syncthreads();
+
+    // moments of the output, summed as the stage stores it
+    CT orho[MOM ? kRows : 1], ojx[MOM ? kRows : 1], ojy[MOM ? kRows : 1];
+    if constexpr (MOM) {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) orho[r] = ojx[r] = ojy[r] = CT(0);
+    }
 
     const int c0 = (wy * kRows + kHalo) * kLX + lx + kHalo;  // LDS cell of the thread's first node
     const int xr = tid / (kTX / kSeg), xs = tid % (kTX / kSeg);   // x-face row and segment
@@ -568,11 +615,31 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                     b = gnv[r];
                 res = fmaT(cb, res - b, b);
             }
-            if (active(r)) {
-                uint32_t rb = 0;
-                if constexpr (std::is_same<T, __half>::value)
-                    rb = mix32((uint32_t)((gy0 + r) * Nx + gx), p.salt ^ ((uint32_t)k * 0x632be5abu));
-                IO::store(ok, node_off(r), res, rb >> 19);
+            uint32_t rb = 0;
+            if constexpr (std::is_same<T, __half>::value)
+                rb = mix32((uint32_t)((gy0 + r) * Nx + gx), p.salt ^ ((uint32_t)k * 0x632be5abu));
+            const auto bits = IO::pack(res, rb >> 19);
+            if constexpr (MOM) {
+                const CT st = IO::unpack(bits);
+                orho[r] += st;
+                ojx[r] = fmaT(st, vxk, ojx[r]);
+                ojy[r] = fmaT(st, vyk, ojy[r]);
+            }
+            if (active(r)) IO::put(ok, node_off(r), bits);
+        }
+        if constexpr (MOM) {
+            if (k == p.K - 1) {
+                char *mb = reinterpret_cast<char *>(out) + moff;
+                const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
+                           m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
+#pragma unroll
+                for (int r = 0; r < kRows; ++r)
+                    if (active(r)) {
+                        const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
+                        MIO::store(m0, o, orho[r], 0);
+                        MIO::store(m1, o, ojx[r], 0);
+                        MIO::store(m2, o, ojy[r], 0);
+                    }
             }
         }
 

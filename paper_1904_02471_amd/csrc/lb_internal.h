@@ -133,10 +133,29 @@ inline unsigned mix_host(unsigned x)
 }
 
 // Store of a stepped state value: FP16 storage rounds stochastically with the
-// given 13 random bits, the other storage types round to nearest.
-__device__ __forceinline__ void store_state(float *p, float v, uint32_t) { *p = v; }
-__device__ __forceinline__ void store_state(double *p, double v, uint32_t) { *p = v; }
-__device__ __forceinline__ void store_state(__half *p, float v, uint32_t r13) { *p = half_sr(v, r13); }
+// given 13 random bits, the other storage types round to nearest.  Returns
+// the value stored, in the arithmetic type.
+__device__ __forceinline__ float store_state(float *p, float v, uint32_t) { *p = v; return v; }
+__device__ __forceinline__ double store_state(double *p, double v, uint32_t) { *p = v; return v; }
+__device__ __forceinline__ float store_state(__half *p, float v, uint32_t r13)
+{
+    const __half h = half_sr(v, r13);
+    *p = h;
+    return __half2float(h);
+}
+
+// Moment planes of a finite-difference state buffer.  After the K population
+// planes (plane elements each) the buffer holds three planes in the
+// arithmetic type: drho = sum_k g_k, jx = sum_k v_kx g_k, jy = sum_k v_ky g_k
+// of the stored values, summed over k in ascending order with one add and two
+// fmas per population, so that they equal bit for bit what a kernel would
+// sum from the planes themselves.  Every kernel that writes a state buffer's
+// populations writes its moment planes too; the stage kernels read them
+// instead of summing the populations again.  Byte offset of the first one:
+__host__ __device__ inline unsigned long long fd_mom_offset(int K, long long plane, int esize)
+{
+    return ((unsigned long long)K * (unsigned long long)plane * (unsigned long long)esize + 255ull) & ~255ull;
+}
 
 template <typename T> struct Arith { using type = float; };
 template <> struct Arith<double> { using type = double; };
@@ -166,6 +185,10 @@ hipError_t launch_fd_stage(const T *src, const T *gn, T *out, int stage, const P
 template <typename T>
 hipError_t launch_fd_imex(int which, T *a_buf, const T *g, T *b_buf, const Params<typename Arith<T>::type> &p,
                           double dt_over_tau, hipStream_t s);
+// Moment planes of the FD state buffer g from its populations (after the
+// populations are set from the host).
+template <typename T>
+hipError_t launch_fd_moments(T *g, const Params<typename Arith<T>::type> &p, hipStream_t s);
 int cs_diag_blocks(int Nx, int Ny);
 int fd_diag_blocks(int Nx, int Ny);
 
