@@ -25,8 +25,7 @@ __global__ __launch_bounds__(kFdThreads) void fd_stage_kernel(const T *__restric
     const int b = blockIdx.x, q = nb / 8, r = nb % 8, x = b % 8;
     const int tile = x * q + (x < r ? x : r) + b / 8;
     const int tiles_x = (p.Nx + kTX - 1) / kTX;
-    fd_stage_tile<T, N, FIXED, WITH_GN, ROWS, true>(src, gn, out, cb, p, d, tile % tiles_x, tile / tiles_x, tile,
-                                                    DIAG);
+    fd_stage_tile<T, N, FIXED, WITH_GN, ROWS>(src, gn, out, cb, p, d, tile % tiles_x, tile / tiles_x, tile, DIAG);
 }
 
 // Moments of a stored value v of population k, accumulated in ascending k

@@ -23,8 +23,7 @@
 //   tile height is a template parameter, 64 x 16 with 4 rows per thread is
 //   the other choice of the autotuner, with 4-face x segments).
 //   1. moments: the thread reads drho, j_x, j_y of its 8 nodes from the
-//      input's moment planes (the batched kernels sum them from the K
-//      populations instead: the same values) and keeps drho, u_x, u_y.
+//      input's moment planes (fd_mom_offset) and keeps drho, u_x, u_y.
 //   2. loop over the populations k; the tile of population k with a 3-node
 //      halo is staged in LDS (double-buffered; the next tile is prefetched
 //      into registers while the current one is used):
@@ -296,10 +295,9 @@ __device__ __forceinline__ CT fd_geq(CT wk, const CT (&hx)[N + 1], const CT (&hy
 // workgroup; with `diag` the diagnostics of the tile's input state go to
 // partial[diag_block].  Every face and node is evaluated by the same
 // sequence of operations for any ROWS, so the stage output does not depend
-// on the tile height.  MOM: the moments of the input come from its moment
-// planes (fd_mom_offset), and the stage writes those of its output; without
-// it the moments are summed from the input's populations (the same values).
-template <typename T, int N, bool FIXED, bool WITH_GN, int ROWS = kFdRows, bool MOM = false>
+// on the tile height.  The moments of the input come from its moment planes
+// (fd_mom_offset), and the stage writes those of its output.
+template <typename T, int N, bool FIXED, bool WITH_GN, int ROWS = kFdRows>
 __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T *gn, T *out,
                                               const typename Arith<T>::type cb,
                                               const Params<typename Arith<T>::type> &p,
@@ -408,7 +406,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     CT drho[kRows], uxv[kRows], uyv[kRows];
     {
         CT jx[kRows], jy[kRows];
-        if constexpr (MOM) {
+        {
             const char *mb = reinterpret_cast<const char *>(src) + moff;
             const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
                        m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
@@ -418,21 +416,6 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 drho[r] = MIO::load(m0, o);
                 jx[r] = MIO::load(m1, o);
                 jy[r] = MIO::load(m2, o);
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < kRows; ++r) drho[r] = jx[r] = jy[r] = CT(0);
-#pragma unroll 2
-            for (int k = 0; k < p.K; ++k) {
-                const CT vxk = p.vx[k], vyk = p.vy[k];
-                const auto sk = fd_plane(src + k * P, pbytes);
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) {
-                    const CT g = IO::load(sk, node_off(r));
-                    drho[r] += g;
-                    jx[r] = fmaT(g, vxk, jx[r]);
-                    jy[r] = fmaT(g, vyk, jy[r]);
-                }
             }
         }
         DiagAcc acc;
@@ -478,11 +461,9 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     __syncthreads();
 
     // moments of the output, summed as the stage stores it
-    CT orho[MOM ? kRows : 1], ojx[MOM ? kRows : 1], ojy[MOM ? kRows : 1];
-    if constexpr (MOM) {
+    CT orho[kRows], ojx[kRows], ojy[kRows];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) orho[r] = ojx[r] = ojy[r] = CT(0);
-    }
+    for (int r = 0; r < kRows; ++r) orho[r] = ojx[r] = ojy[r] = CT(0);
 
     const int c0 = (wy * kRows + kHalo) * kLX + lx + kHalo;  // LDS cell of the thread's first node
     const int xr = tid / (kTX / kSeg), xs = tid % (kTX / kSeg);   // x-face row and segment
@@ -619,28 +600,26 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             if constexpr (std::is_same<T, __half>::value)
                 rb = mix32((uint32_t)((gy0 + r) * Nx + gx), p.salt ^ ((uint32_t)k * 0x632be5abu));
             const auto bits = IO::pack(res, rb >> 19);
-            if constexpr (MOM) {
-                const CT st = IO::unpack(bits);
-                orho[r] += st;
-                ojx[r] = fmaT(st, vxk, ojx[r]);
-                ojy[r] = fmaT(st, vyk, ojy[r]);
-            }
+            const CT st = IO::unpack(bits);
+            orho[r] += st;
+            ojx[r] = fmaT(st, vxk, ojx[r]);
+            ojy[r] = fmaT(st, vyk, ojy[r]);
             if (active(r)) IO::put(ok, node_off(r), bits);
         }
-        if constexpr (MOM) {
-            if (k == p.K - 1) {
-                char *mb = reinterpret_cast<char *>(out) + moff;
-                const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
-                           m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
+        // the output's moments, after its last population (inside the loop:
+        // stored after it, they kept other registers live and cost more)
+        if (k == p.K - 1) {
+            char *mb = reinterpret_cast<char *>(out) + moff;
+            const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
+                       m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
 #pragma unroll
-                for (int r = 0; r < kRows; ++r)
-                    if (active(r)) {
-                        const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
-                        MIO::store(m0, o, orho[r], 0);
-                        MIO::store(m1, o, ojx[r], 0);
-                        MIO::store(m2, o, ojy[r], 0);
-                    }
-            }
+            for (int r = 0; r < kRows; ++r)
+                if (active(r)) {
+                    const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
+                    MIO::store(m0, o, orho[r], 0);
+                    MIO::store(m1, o, ojx[r], 0);
+                    MIO::store(m2, o, ojy[r], 0);
+                }
         }
 
         // d. next tile into the other LDS buffer, prefetch the one after

@@ -54,9 +54,7 @@ def single_run(e):
 
 def test_alone_equals_in_the_mix():
     """Served results equal alone and in a mix, and equal the single-simulation
-    path bit for bit.  For the FD requests this also checks that the moment
-    planes the single-simulation stages carry from stage to stage hold exactly
-    the sums that the batched stages form from the populations."""
+    path bit for bit."""
     print("case: serving alone vs mix", flush=True)
     mix = small_mix()
     alone = run_server([mix[0]])[0]
