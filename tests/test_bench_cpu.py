@@ -1,0 +1,44 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract and the reporting
+of measured kernel traffic only while the kernel's sources are unchanged."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
+    bench = load_bench()
+    csrc = os.path.join(ROOT, "paper_1904_02471_amd", "csrc")
+    files = ["lb_fd_impl.h", "lb_fd.hip"]
+    record = {"fd_stage_kernel": {"grid": [64, 64], "bytes_per_launch": 12345, "sources": files,
+                                  "sources_sha256": bench.source_digest(files)}}
+    pkg = tmp_path / "paper_1904_02471_amd"
+    (pkg / "csrc").mkdir(parents=True)
+    for f in files:
+        (pkg / "csrc" / f).write_bytes(open(os.path.join(csrc, f), "rb").read())
+    (pkg / "kernel_traffic.json").write_text(json.dumps(record))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_traffic("fd_stage_kernel", 64) == 12345
+    assert bench.kernel_traffic("fd_stage_kernel", 128) is None  # another workload
+    assert bench.kernel_traffic("cs_step_vec_kernel", 64) is None  # no record
+    with open(pkg / "csrc" / "lb_fd.hip", "ab") as fh:  # the kernel changed since the counters
+        fh.write(b"\n// edited\n")
+    assert bench.kernel_traffic("fd_stage_kernel", 64) is None
