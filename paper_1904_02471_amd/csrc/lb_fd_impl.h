@@ -137,9 +137,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t fd_plane(const void *base, uin
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
 }
 
-// Loads and stores of stored state values at a byte offset of a plane;
-// stores round as store_state does (stochastically to FP16 with r13) and
-// return the value stored.
+// Loads and stores of values at a byte offset of a plane (FP32 and FP64:
+// also the moment planes).  pack gives the bits a stepped value is stored
+// as (rounded as store_state does: stochastically to FP16 with r13), unpack
+// their value, put stores them.
 template <typename T>
 struct FdPlaneIO;
 template <>
@@ -148,14 +149,13 @@ struct FdPlaneIO<float> {
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     }
-    static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t)
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
-        return v;
     }
     static __device__ __forceinline__ float pack(float v, uint32_t) { return v; }
     static __device__ __forceinline__ float unpack(float b) { return b; }
-    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, float b) { store(r, off, b, 0); }
+    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, float b) { store(r, off, b); }
 };
 template <>
 struct FdPlaneIO<double> {
@@ -164,14 +164,13 @@ struct FdPlaneIO<double> {
     {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
     }
-    static __device__ __forceinline__ double store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, uint32_t)
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
     {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, off, 0, 0);
-        return v;
     }
     static __device__ __forceinline__ double pack(double v, uint32_t) { return v; }
     static __device__ __forceinline__ double unpack(double b) { return b; }
-    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, double b) { store(r, off, b, 0); }
+    static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, double b) { store(r, off, b); }
 };
 template <>
 struct FdPlaneIO<__half> {
@@ -179,14 +178,6 @@ struct FdPlaneIO<__half> {
     {
         return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
     }
-    static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, uint32_t r13)
-    {
-        const __half h = half_sr(v, r13);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, off, 0, 0);
-        return __half2float(h);
-    }
-    // the stored bits of v (rounded stochastically with r13), their value,
-    // and their store
     static __device__ __forceinline__ __half pack(float v, uint32_t r13) { return half_sr(v, r13); }
     static __device__ __forceinline__ float unpack(__half b) { return __half2float(b); }
     static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t off, __half b)
@@ -405,18 +396,17 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         fetch(0, pre);
     CT drho[kRows], uxv[kRows], uyv[kRows];
     {
+        // the input's moments, from its moment planes
         CT jx[kRows], jy[kRows];
-        {
-            const char *mb = reinterpret_cast<const char *>(src) + moff;
-            const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
-                       m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
+        const char *mb = reinterpret_cast<const char *>(src) + moff;
+        const auto m0 = fd_plane(mb, mbytes), m1 = fd_plane(mb + mbytes, mbytes),
+                   m2 = fd_plane(mb + 2 * (unsigned long long)mbytes, mbytes);
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) {
-                const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
-                drho[r] = MIO::load(m0, o);
-                jx[r] = MIO::load(m1, o);
-                jy[r] = MIO::load(m2, o);
-            }
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
+            drho[r] = MIO::load(m0, o);
+            jx[r] = MIO::load(m1, o);
+            jy[r] = MIO::load(m2, o);
         }
         DiagAcc acc;
         CT pax = CT(0), pbx = CT(0);
@@ -616,9 +606,9 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             for (int r = 0; r < kRows; ++r)
                 if (active(r)) {
                     const uint32_t o = node_idx(r) * (uint32_t)sizeof(CT);
-                    MIO::store(m0, o, orho[r], 0);
-                    MIO::store(m1, o, ojx[r], 0);
-                    MIO::store(m2, o, ojy[r], 0);
+                    MIO::store(m0, o, orho[r]);
+                    MIO::store(m1, o, ojx[r]);
+                    MIO::store(m2, o, ojy[r]);
                 }
         }
 
