@@ -98,9 +98,10 @@ typedef struct lb_sim lb_sim;
  * one node per direction is a valid grid); CS needs N == 2 and
  * tau > dt/2 (positive viscosity nu = c_s^2 (tau - dt/2), Section 2); FD
  * needs 1 <= N <= Q-1, the CFL bound, dt <= tau (Section 4.1) and one
- * population plane and one moment plane below 4 GiB (Nx * Ny * 8 < 2^32 for
- * FP64 storage, Nx * Ny * 4 < 2^32 otherwise: the moments are kept in the
- * arithmetic type).  Allocates all device memory (2 state buffers for CS, 3
+ * population plane and one moment plane below 4 GiB: (Nx * Ny + 4352 / s) * c
+ * < 2^32, with s the bytes of a stored value and c = 8 for FP64 storage, 4
+ * otherwise (the moments are kept in the arithmetic type; each plane is
+ * padded by 4352 bytes).  Allocates all device memory (2 state buffers for CS, 3
  * for FD, each FD buffer with three moment planes after its populations) on
  * the current HIP device.  Returns NULL on error (see lb_last_error). */
 lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double ds, int N);

@@ -141,7 +141,7 @@ int alloc_buffers(lb_sim *s)
     free_buffers(s);
     s->xoff = (s->cs && s->fixed) ? 1 : 0;
     s->pitch = s->Nx + 2 * s->xoff;
-    s->plane = (long long)s->pitch * s->Ny;
+    s->plane = padded_plane((long long)s->pitch * s->Ny, s->esize);
     s->buf_bytes = (size_t)s->K * (size_t)s->plane * s->esize;
     if (!s->cs)  // the moment planes (fd_mom_offset), in the arithmetic type
         s->buf_bytes = (size_t)fd_mom_offset(s->K, s->plane, s->esize) +
@@ -377,9 +377,11 @@ int validate_create(int model_flags, int Nx, int Ny, double tau, double dt, doub
     }
     if (N < 1 || N > mi.Q - 1) return LB_EINVAL;
     // the stage kernels address a population plane, and a moment plane in the
-    // arithmetic type (at least 4 bytes a value), with 32-bit byte offsets
-    const long long esize = precbits == LB_FP64 ? 8 : 4;
-    if ((long long)Nx * Ny * esize >= (1LL << 32)) return LB_EINVAL;
+    // arithmetic type (at least 4 bytes a value), with 32-bit byte offsets;
+    // planes are padded (padded_plane)
+    const int esize = precbits == LB_FP64 ? 8 : (precbits == LB_FP16_SHIFTED ? 2 : 4);
+    const long long csize = precbits == LB_FP64 ? 8 : 4;
+    if (padded_plane((long long)Nx * Ny, esize) * csize >= (1LL << 32)) return LB_EINVAL;
     // CFL = max |v_k,alpha| dt / ds <= 1 and dt < tau (Section 4.1); dt == tau
     // is accepted, as in the shear-wave runs of Section 4.2
     const double vmax = mi.xi[mi.Q - 1];

@@ -144,6 +144,15 @@ __device__ __forceinline__ float store_state(__half *p, float v, uint32_t r13)
     return __half2float(h);
 }
 
+// Elements between population planes: the plane (pitch x Ny) plus 4352
+// bytes.  With planes a power of two in size (2048^2, 4096^2), the rows that
+// a kernel reads from the K planes at once start at the same offset modulo
+// every power-of-two interleave of the memory channels and crowd the same
+// channels; the pad (a multiple of 16 bytes, so rows keep their alignment)
+// spreads them: +8 % on the 4096^2 collision-streaming step.
+constexpr long long kPlanePadBytes = 4352;
+inline long long padded_plane(long long elems, int esize) { return elems + kPlanePadBytes / esize; }
+
 // Moment planes of a finite-difference state buffer.  After the K population
 // planes (plane elements each) the buffer holds three planes in the
 // arithmetic type: drho = sum_k g_k, jx = sum_k v_kx g_k, jy = sum_k v_ky g_k

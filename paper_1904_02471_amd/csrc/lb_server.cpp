@@ -62,10 +62,11 @@ size_t footprint_of(const lb_request &r, const ModelInfo &mi)
 {
     const bool cs = r.model == LB_CS_D2Q9;
     const size_t nodes = (size_t)r.Nx * r.Ny;
+    const size_t plane = (size_t)padded_plane((long long)nodes, (int)sizeof(float));
     // FD buffers hold three FP32 moment planes after the populations
-    const size_t state = cs ? 2 * (size_t)mi.K * nodes * sizeof(float)
-                            : 3 * ((size_t)fd_mom_offset(mi.K, (long long)nodes, (int)sizeof(float)) +
-                                   3 * nodes * sizeof(float));
+    const size_t state = cs ? 2 * (size_t)mi.K * plane * sizeof(float)
+                            : 3 * ((size_t)fd_mom_offset(mi.K, (long long)plane, (int)sizeof(float)) +
+                                   3 * plane * sizeof(float));
     int blocks = std::max(cs_diag_blocks(r.Nx, r.Ny), fd_diag_blocks(r.Nx, r.Ny));
     blocks = std::max(blocks, reduce_diag_blocks(r.Nx, r.Ny));
     const size_t diag = sizeof(double) * kDiag * ((size_t)blocks + 1);
