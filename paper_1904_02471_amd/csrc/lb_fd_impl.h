@@ -311,6 +311,9 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     const int tid = threadIdx.x;
     const int lx = tid & 63, wy = tid >> 6;
     const int cw = diag_block & 3;  // wave of the column-0 x-faces
+    // that wave has the tile-edge faces to evaluate on top of its share, and
+    // the others wait for it at the barriers: let its instructions go first
+    if (wy == cw) __builtin_amdgcn_s_setprio(2);
     const int x0 = bx * kTX, y0 = by * kTY;
     const int Nx = p.Nx, Ny = p.Ny;
     const long long P = p.plane;
