@@ -1,6 +1,6 @@
 """Build the FP64 CPU oracle shared library (test infrastructure).
 
-Plain gcc, no GPU code, no shared sources with the GPU library.
+Plain gcc (with OpenMP for the optional row-parallel mode), no GPU code, no shared sources with the GPU library.
 """
 import os
 import subprocess
@@ -15,8 +15,10 @@ def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
+    # -fopenmp: the optional row-parallel mode (orc_set_threads); one thread
+    # by default
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-ffp-contract=off", SRC, "-o", tmp, "-lm"]
+           "-ffp-contract=off", "-fopenmp", SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

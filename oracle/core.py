@@ -39,6 +39,7 @@ def _load():
     lib.orc_sound_speed.restype = ctypes.c_double
     lib.orc_velocities.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
     lib.orc_set_weno_eps.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    lib.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc_set_time_scheme.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc_set_bc_x.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
     lib.orc_equilibrium.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -125,6 +126,11 @@ class OracleSim:
 
     def set_weno_eps(self, eps):
         self._lib.orc_set_weno_eps(self._h, eps)
+
+    def set_threads(self, threads):
+        """Host threads of the row and node loops (1, the default, is the plain
+        serial run); the results are bitwise the same for any count."""
+        self._lib.orc_set_threads(self._h, int(threads))
 
     def set_time_scheme(self, scheme):
         """FD only: 0 third-order TVD Runge-Kutta, 1 IMEX-SSP2(2,2,2) (advection

@@ -10,8 +10,14 @@
  * (Gauss-Hermite roots and weights, Hermite polynomials) itself.
  *
  * Everything is written for clarity, not speed: one node, one population at a
- * time, in double precision, single threaded, in the order the paper states
- * the steps.  Readings taken where the paper is silent are marked READING.
+ * time, in double precision, in the order the paper states the steps.  By
+ * default it runs on one thread (the plain definition); orc_set_threads lets
+ * the loops over rows and nodes run on several host threads (OpenMP), which
+ * changes no arithmetic: every node's values are computed by the same
+ * operations whichever thread takes it, so the results are bitwise those of
+ * the single-threaded run.  Sums over the whole lattice (orc_reduce) stay on
+ * one thread, in node order.  Readings taken where the paper is silent are
+ * marked READING.
  *
  * Distribution layout: f[k][y][x], x fastest, k the population index.
  *   CS D2Q9 population order: 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
@@ -37,7 +43,12 @@ typedef struct orc_sim {
     double rho_left, rho_right;
     double weno_eps;
     int time_scheme; /* FD: 0 third-order TVD Runge-Kutta, 1 IMEX-SSP2(2,2,2) */
+    int threads;     /* host threads of the row / node loops (1: plain serial run) */
 } orc_sim;
+
+/* Row / node loops of a function whose simulation is `s`: parallel over
+ * s->threads host threads when above one. */
+#define ORC_PARALLEL_FOR _Pragma("omp parallel for num_threads(s->threads) if(s->threads > 1) schedule(static)")
 
 /* ------------------------------------------------------------------------ */
 /* Gauss-Hermite quadrature (Section 1: the velocity set is given by the     */
@@ -215,6 +226,7 @@ orc_sim *orc_create(int model, int Nx, int Ny, double tau, double dt, double ds,
     s->ds = ds;
     s->N = N;
     s->weno_eps = 1e-6;
+    s->threads = 1;
     int K = orc_velocity_set(model, ds, dt, s->vx, s->vy, s->w, &s->cs, s->ex, s->ey);
     if (K < 0) { free(s); return NULL; }
     s->K = K;
@@ -241,6 +253,10 @@ void orc_velocities(const orc_sim *s, double *vx, double *vy, double *w)
 
 void orc_set_weno_eps(orc_sim *s, double eps) { s->weno_eps = eps; }
 
+/* Host threads of the row and node loops (>= 1; 1 is the plain serial run).
+ * Results do not depend on it. */
+void orc_set_threads(orc_sim *s, int threads) { s->threads = threads < 1 ? 1 : threads; }
+
 /* Fixed-value x ends: the nodes beyond x = 0 and x = Nx-1 hold the
  * equilibrium at (rho_left, 0) and (rho_right, 0).  READING: the paper runs
  * every case periodic; this equilibrium (Dirichlet) end is the reading used
@@ -261,6 +277,7 @@ void orc_equilibrium(const orc_sim *s, double rho, double ux, double uy, double 
 void orc_init(orc_sim *s, const double *rho, const double *ux, const double *uy)
 {
     long plane = (long)s->Nx * s->Ny;
+    ORC_PARALLEL_FOR
     for (long node = 0; node < plane; ++node)
         for (int k = 0; k < s->K; ++k) s->f[k * plane + node] = feq_one(s, k, rho[node], ux[node], uy[node]);
 }
@@ -278,6 +295,7 @@ void orc_set_state(orc_sim *s, const double *f)
 void orc_moments(const orc_sim *s, double *rho, double *ux, double *uy)
 {
     long plane = (long)s->Nx * s->Ny;
+    ORC_PARALLEL_FOR
     for (long node = 0; node < plane; ++node) moments_node(s, s->f, node, plane, &rho[node], &ux[node], &uy[node]);
 }
 
@@ -293,6 +311,7 @@ static void cs_step_once(orc_sim *s)
     long plane = (long)Nx * Ny;
     double *fstar = s->work[0];
     double omega = s->dt / s->tau;
+    ORC_PARALLEL_FOR
     for (long node = 0; node < plane; ++node) {
         double rho, ux, uy;
         moments_node(s, s->f, node, plane, &rho, &ux, &uy);
@@ -301,7 +320,8 @@ static void cs_step_once(orc_sim *s)
             fstar[k * plane + node] = fk - omega * (fk - feq_one(s, k, rho, ux, uy));
         }
     }
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+        ORC_PARALLEL_FOR
         for (int y = 0; y < Ny; ++y)
             for (int x = 0; x < Nx; ++x) {
                 int xs = x - s->ex[k], ys = y - s->ey[k];
@@ -315,6 +335,7 @@ static void cs_step_once(orc_sim *s)
                 }
                 s->f[k * plane + (long)y * Nx + x] = val;
             }
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -374,6 +395,7 @@ static void fd_rhs(const orc_sim *s, const double *f, double *out)
 {
     int Nx = s->Nx, Ny = s->Ny, K = s->K;
     long plane = (long)Nx * Ny;
+    ORC_PARALLEL_FOR
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             long node = (long)y * Nx + x;
@@ -407,10 +429,13 @@ static void fd_step_once(orc_sim *s)
     double *L = s->work[0], *f1 = s->work[1], *f2 = s->work[2];
     double dt = s->dt;
     fd_rhs(s, s->f, L);
+    ORC_PARALLEL_FOR
     for (long i = 0; i < n; ++i) f1[i] = s->f[i] + dt * L[i];
     fd_rhs(s, f1, L);
+    ORC_PARALLEL_FOR
     for (long i = 0; i < n; ++i) f2[i] = 0.75 * s->f[i] + 0.25 * (f1[i] + dt * L[i]);
     fd_rhs(s, f2, L);
+    ORC_PARALLEL_FOR
     for (long i = 0; i < n; ++i) s->f[i] = s->f[i] / 3.0 + 2.0 / 3.0 * (f2[i] + dt * L[i]);
 }
 
@@ -434,6 +459,7 @@ static void fd_advection(const orc_sim *s, const double *f, double *out)
 {
     int Nx = s->Nx, Ny = s->Ny, K = s->K;
     long plane = (long)Nx * Ny;
+    ORC_PARALLEL_FOR
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             long node = (long)y * Nx + x;
@@ -458,6 +484,7 @@ static void fd_advection(const orc_sim *s, const double *f, double *out)
 static void fd_relaxation(const orc_sim *s, const double *f, double *out)
 {
     long plane = (long)s->Nx * s->Ny;
+    ORC_PARALLEL_FOR
     for (long node = 0; node < plane; ++node) {
         double rho, ux, uy;
         moments_node(s, f, node, plane, &rho, &ux, &uy);
@@ -470,6 +497,7 @@ static void fd_relaxation(const orc_sim *s, const double *f, double *out)
 static void fd_implicit_relax(const orc_sim *s, const double *h, double a, double *out)
 {
     long plane = (long)s->Nx * s->Ny;
+    ORC_PARALLEL_FOR
     for (long node = 0; node < plane; ++node) {
         double rho, ux, uy;
         moments_node(s, h, node, plane, &rho, &ux, &uy);
