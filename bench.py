@@ -16,7 +16,8 @@ and HBM fractions, the roofline of the dominant kernel (the FD stage), the
 CS step at 4096^2 with FP32 and FP16-shifted storage (states larger than the
 last-level cache, so those byte rates are HBM rates), the FD D2Q36 step at
 2048^2, the serving stream,
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+and the FP64 CPU oracle timed on bounded samples of the same workload (all
+usable host threads, and one thread).
 """
 import argparse
 import json
@@ -29,12 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# FP32 vector peak without packed FP32 instructions (the library is built
-# without them): 256 CUs x 64 lanes x 2 flop per fma x 2.4 GHz.  The
-# published 157.3 TFLOP/s counts packed (two-wide) FP32 instructions.
-VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Published FP32 vector peak of MI355X (counts packed two-wide FP32
+# instructions).  The library is built without packed FP32 instructions, so
+# the FP32 rate it can issue is half of it: 256 CUs x 64 lanes x 2 flop per
+# fma x 2.4 GHz = 78.6 TFLOP/s, reported beside the published fraction.
 VALU_PEAK_PUBLISHED_TFLOPS = 157.3
+VALU_PEAK_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # Algorithmic flops of the FD D2Q16 (N = 3) stage, fma counted as 2: per
 # node and population the x- and y-face WENO-5 values (47 each, with the
 # second differences, smoothness terms and first differences of a cell
@@ -173,36 +175,70 @@ def kernel_traffic(kernel, n):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(every):
-    """FP64 oracle on a bounded sample of the same workload (about 15 s of one
-    core): CS D2Q9 512^2 x 48 steps and FD D2Q16 256^2 x 12 steps, diagnostics
-    every `every` steps."""
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo) and the threads this
+    process may use, capped at the 16 host threads a one-GPU machine shares."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail, max(1, min(16, avail))
+
+
+def cpu_baseline(every, n):
+    """FP64 oracle timed on the host on bounded samples of the same workload:
+    the row-parallel mode on all usable host threads (bitwise the serial
+    run) on the n x n grid itself, 2 CS D2Q9 steps + 1 FD D2Q16 step; and
+    the plain serial run on 1024^2 x 3 CS steps + 512^2 x 2 FD steps (same
+    work per node).  Diagnostics every `every` steps as on the GPU.  value =
+    node updates per second of the all-thread run, one update = one CS step
+    plus one FD step per node: 1 / (t_cs + t_fd) per node."""
     import oracle
     from paper_1904_02471_amd import units, workloads
 
-    def run(model, n, steps):
+    def run(model, m, steps, threads):
         if model == oracle.CS_D2Q9:
-            s = oracle.OracleSim(model, n, n, 0.6, 1.0, 1.0, 2)
-            r, ux, uy, (px, py) = workloads.taylor_green(n, n, 0.01, 1.0 / 3.0)
+            s = oracle.OracleSim(model, m, m, 0.6, 1.0, 1.0, 2)
+            r, ux, uy, (px, py) = workloads.taylor_green(m, m, 0.01, 1.0 / 3.0)
         else:
-            ds = 1.0 / n
-            tau = units.tau_fd_from_std(0.6, n)
-            s = oracle.OracleSim(model, n, n, tau, units.fd_time_step(tau, ds, 2.3344142183389773, 0.5), ds, 3)
-            r, ux, uy, (px, py) = workloads.taylor_green(n, n, units.velocity_fd_from_std(0.01), 1.0)
+            ds = 1.0 / m
+            tau = units.tau_fd_from_std(0.6, m)
+            s = oracle.OracleSim(model, m, m, tau, units.fd_time_step(tau, ds, 2.3344142183389773, 0.5), ds, 3)
+            r, ux, uy, (px, py) = workloads.taylor_green(m, m, units.velocity_fd_from_std(0.01), 1.0)
+        s.set_threads(threads)
         s.init(r, ux, uy)
+        del r, ux, uy
         t0 = time.perf_counter()
         for i in range(steps):
             if i % every == 0:
                 s.reduce(px, py)
             s.step(1)
-        return (time.perf_counter() - t0) / (n * n * steps)
+        t = (time.perf_counter() - t0) / (m * m * steps)
+        s.close()
+        return t
 
-    t_cs = run(oracle.CS_D2Q9, 512, 48)
-    t_fd = run(oracle.FD_D2Q16, 256, 12)
-    return {"value": 1e-6 / (t_cs + t_fd), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "FP64 C oracle, single thread: CS D2Q9 TGV 512x512 x 48 steps (%.3f MLUPS) + "
-                      "FD D2Q16 TGV 256x256 x 12 steps (%.4f MLUPS), diagnostics every %d steps; value = "
-                      "1 / (t_cs + t_fd) per node" % (1e-6 / t_cs, 1e-6 / t_fd, every)}
+    model_name, avail, threads = host_cpu()
+    t_cs = run(oracle.CS_D2Q9, n, 2, threads)
+    t_fd = run(oracle.FD_D2Q16, n, 1, threads)
+    s_cs = run(oracle.CS_D2Q9, 1024, 3, 1)
+    s_fd = run(oracle.FD_D2Q16, 512, 2, 1)
+    return {"value": 1e-6 / (t_cs + t_fd), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "FP64 C oracle, row-parallel on %d host threads (bitwise the serial run): CS D2Q9 TGV "
+                      "%dx%d x 2 steps (%.3f MLUPS) + FD D2Q16 TGV %dx%d x 1 step (%.4f MLUPS); value = "
+                      "1 / (t_cs + t_fd) per node" % (threads, n, n, 1e-6 / t_cs, n, n, 1e-6 / t_fd),
+            "cpu_model": model_name, "host_threads_available": avail,
+            "single_thread": {"value": 1e-6 / (s_cs + s_fd), "unit": "MLUPS", "cores": 1,
+                              "sample": "serial: CS D2Q9 TGV 1024x1024 x 3 steps (%.3f MLUPS) + FD D2Q16 TGV "
+                                        "512x512 x 2 steps (%.4f MLUPS)" % (1e-6 / s_cs, 1e-6 / s_fd)}}
 
 
 def serving_bench(n_requests, every):
@@ -390,16 +426,30 @@ def main():
                      "bytes_per_node_step": 512},
     }
     if run_fd:
-        # the FD stage dominates the step and is bound by vector ALU issue
+        # The FD stage dominates the step.  Its two roofs, both against
+        # published peaks: HBM (the stage-wise algorithmic bytes, 8 K s per
+        # step = 8/3 K s per stage launch) and the FP32 vector ALU (the
+        # algorithmic flops).  The binding roof is the one with the higher
+        # fraction.  Launch duration: the FD step time over its three stage
+        # launches (events on the launch stream around the FD steps).
         flops_launch = nodes * (16 * sum(FD16_FLOPS_NODE_POP) / 3.0 + FD16_FLOPS_NODE)
         tflops = flops_launch / (fd_stage_ms * 1e-3) / 1e12
-        line["roofline"] = {
-            "kernel": "fd_stage_kernel", "bound": "alu", "achieved": round(tflops, 2),
-            "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
-            "traffic": kernel_traffic("fd_stage_kernel", n),
-            "flops_per_launch": flops_launch,
-            "frac_of_published_fp32_peak": round(tflops / VALU_PEAK_PUBLISHED_TFLOPS, 4),
-            "hbm_frac_stagewise": round(fd_gbs / HBM_PEAK_GBS, 4)}
+        hbm_frac = fd_gbs / HBM_PEAK_GBS
+        alu_frac = tflops / VALU_PEAK_PUBLISHED_TFLOPS
+        if hbm_frac >= alu_frac:
+            roof = {"bound": "hbm", "achieved": round(fd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_frac, 4)}
+        else:
+            roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_PUBLISHED_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+        line["roofline"] = dict(
+            kernel="fd_stage_kernel", **roof, traffic=kernel_traffic("fd_stage_kernel", n),
+            bytes_per_launch=bytes_fd_stage, flops_per_launch=flops_launch,
+            hbm_frac=round(hbm_frac, 4), alu_frac_published_peak=round(alu_frac, 4),
+            alu_tflops=round(tflops, 2),
+            alu_frac_nonpacked_peak=round(tflops / VALU_PEAK_NONPACKED_TFLOPS, 4),
+            nonpacked_peak="78.6 TFLOP/s = 256 CU x 64 lanes x 2 flop/fma x 2.4 GHz (no packed FP32 "
+                           "instructions in this build)")
     else:
         line["roofline"] = {
             "kernel": "cs_step_vec_kernel", "bound": "hbm", "achieved": round(cs_gbs, 1), "peak": HBM_PEAK_GBS,
@@ -428,7 +478,7 @@ def main():
             fd.destroy()
         line["serving"] = serving_bench(args.serving_requests, every)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(every)
+        line["cpu_baseline"] = cpu_baseline(every, n)
     print(json.dumps(line), flush=True)
 
 

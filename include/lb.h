@@ -142,9 +142,13 @@ int lb_step(lb_sim *sim, int nsteps);
 /* Density and velocity of the current state, [Ny][Nx] each (any may be NULL). */
 int lb_moments(lb_sim *sim, double *rho, double *ux, double *uy);
 
-/* Velocity pattern for the amplitude diagnostic, as products of 1-D
- * factors: phi_x(i, j) = ax[i] ay[j], phi_y(i, j) = bx[i] by[j]
- * (ax, bx: Nx values; ay, by: Ny values).  All NULL clears the pattern. */
+/* Velocity pattern for the amplitude diagnostic of lb_reduce and of the
+ * sampled steps, as products of 1-D factors: phi_x(i, j) = ax[i] ay[j],
+ * phi_y(i, j) = bx[i] by[j] (ax, bx: Nx values; ay, by: Ny values).  All NULL
+ * clears the pattern.  The decaying modes of Sections 4.2-4.3 (shear wave,
+ * Taylor-Green vortex) are of this form, which lets the sampled steps form
+ * the projection from 2 (Nx + Ny) values instead of two full fields; an
+ * arbitrary pattern goes through lb_reduce_field. */
 int lb_set_probe(lb_sim *sim, const double *ax, const double *ay, const double *bx, const double *by);
 
 /* Diagnostics of the current state, accumulated in FP64 on the device in a
@@ -153,6 +157,17 @@ int lb_set_probe(lb_sim *sim, const double *ax, const double *ay, const double *
  *   out[3] E  = sum rho |u|^2/2  out[4] A = sum u.phi / sum phi.phi (0 without a probe)
  * Returns LB_ENAN when a result is not finite. */
 int lb_reduce(lb_sim *sim, double out[5]);
+
+/* Diagnostics of the current state with an arbitrary velocity pattern phi
+ * (the mode whose amplitude the decay laws of Sections 4.2-4.3 follow):
+ * phi_x, phi_y are host arrays [Ny][Nx] (both NULL: A = 0).  Same sums and
+ * order of accumulation as lb_reduce, in FP64 on the device:
+ *   out[0] M = sum rho, out[1..2] P = sum rho u, out[3] E = sum rho |u|^2/2,
+ *   out[4] A = sum u.phi / sum phi.phi (0 when phi.phi sums to 0).
+ * Copies the pattern to a temporary device buffer (allocates) and
+ * synchronises.  LB_EINVAL if only one of phi_x, phi_y is given or a value is
+ * not finite; LB_ENAN when a result is not finite. */
+int lb_reduce_field(lb_sim *sim, const double *phi_x, const double *phi_y, double out[5]);
 
 /* Advance nsteps steps; for every step whose input state has
  * lb_steps_done() % every == 0, the diagnostics of that input state are

@@ -480,7 +480,8 @@ lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double
         blocks = std::max(blocks, fd_diag_blocks(Nx, Ny));
         blocks = std::max(blocks, reduce_diag_blocks(Nx, Ny));
         s->partial_blocks = blocks;
-        if (hipMalloc(&s->d_partial, sizeof(double) * kDiag * (size_t)blocks) != hipSuccess ||
+        // kDiag + 1 sums per block: the field reduction also sums phi . phi
+        if (hipMalloc(&s->d_partial, sizeof(double) * (kDiag + 1) * (size_t)blocks) != hipSuccess ||
             hipMalloc(&s->d_out, sizeof(double) * kDiag) != hipSuccess) {
             (void)hipGetLastError();
             rc = LB_ENOMEM;
@@ -561,7 +562,7 @@ long long lb_steps_done(const lb_sim *s) { return s ? s->steps : -1; }
 size_t lb_device_bytes(const lb_sim *s)
 {
     if (!s) return 0;
-    return s->nbuf * s->buf_bytes + sizeof(double) * kDiag * ((size_t)s->partial_blocks + 1) +
+    return s->nbuf * s->buf_bytes + sizeof(double) * ((kDiag + 1) * (size_t)s->partial_blocks + kDiag) +
            (s->d_probe64 ? 2 * (s->Nx + s->Ny) * (sizeof(double) + sizeof(float)) : 0) +
            sizeof(double) * kDiag * (size_t)s->series_cap;
 }
@@ -868,6 +869,38 @@ int lb_reduce(lb_sim *s, double out[5])
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(dev_status(e));
     finish_diag(s, raw, 1.0, out);
+    if (!all_finite(out, kDiag)) return fail(LB_ENAN);
+    return LB_OK;
+}
+
+int lb_reduce_field(lb_sim *s, const double *phi_x, const double *phi_y, double out[5])
+{
+    if (!s || !out || (!phi_x) != (!phi_y)) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    const size_t n = (size_t)s->Nx * s->Ny;
+    if (phi_x && (!all_finite(phi_x, n) || !all_finite(phi_y, n))) return fail(LB_EINVAL);
+    double *d = nullptr;
+    if (phi_x) {
+        if (hipMalloc(&d, 2 * n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LB_ENOMEM);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (d) e = hipMemcpyAsync(d, phi_x, n * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (d && e == hipSuccess) e = hipMemcpyAsync(d + n, phi_y, n * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        const Params<double> p = make_params<double>(s);
+        e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return launch_reduce_field<T>(bufp<T>(s, state_index(s)), s->cs, p, d, d ? d + n : nullptr,
+                                          s->d_partial, s->d_out, s->stream);
+        });
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, s->d_out, sizeof(double) * kDiag, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (d) (void)hipFree(d);
+    if (e != hipSuccess) return fail(dev_status(e));
     if (!all_finite(out, kDiag)) return fail(LB_ENAN);
     return LB_OK;
 }

@@ -159,6 +159,52 @@ __global__ __launch_bounds__(kAuxThreads) void diag_finalize_kernel(const double
     diag_finalize_block(partial, nblocks, out);
 }
 
+// Diagnostics with a velocity pattern given as two full fields phi_x, phi_y
+// ([Ny][Nx], FP64; both NULL for none): per block the FP64 sums of drho, j_x,
+// j_y, rho |u|^2 / 2, u . phi and phi . phi, in node order per thread.
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void reduce_field_kernel(const T *src, bool cs, const Params<double> p,
+                                                                   const double *phix, const double *phiy,
+                                                                   double *partial)
+{
+    const long long nodes = (long long)p.Nx * p.Ny;
+    double acc[kDiag + 1] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x; n < nodes;
+         n += (long long)gridDim.x * kAuxThreads) {
+        const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+        double drho, jx, jy;
+        node_moments(src, cs, p, x, y, drho, jx, jy);
+        const double r = p.rho0 + drho, ux = jx / r, uy = jy / r;
+        acc[0] += drho;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += 0.5 * r * (ux * ux + uy * uy);
+        if (phix) {
+            const double a = phix[n], b = phiy[n];
+            acc[4] += ux * a + uy * b;
+            acc[5] += a * a + b * b;
+        }
+    }
+    block_sum_store<kDiag + 1>(acc, partial, blockIdx.x);
+}
+
+// {M, Px, Py, E, A} from the partials of reduce_field_kernel: M = rho0 nodes
+// + sum drho, A = sum u.phi / sum phi.phi (0 without a pattern).
+__global__ __launch_bounds__(kAuxThreads) void reduce_field_finish_kernel(const double *partial, int nblocks,
+                                                                          double rho0, double nodes, double *out)
+{
+    __shared__ double sums[kDiag + 1];
+    finalize_sums_block<kDiag + 1>(partial, nblocks, sums);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = rho0 * nodes + sums[0];
+        out[1] = sums[1];
+        out[2] = sums[2];
+        out[3] = sums[3];
+        out[4] = sums[5] > 0.0 ? sums[4] / sums[5] : 0.0;
+    }
+}
+
 unsigned grid_for(long long n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
 
 }  // namespace
@@ -220,6 +266,17 @@ hipError_t launch_reduce(const T *src, bool cs, const Params<double> &p, const D
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_reduce_field(const T *src, bool cs, const Params<double> &p, const double *phix, const double *phiy,
+                               double *partial, double *out, hipStream_t s)
+{
+    const int nb = reduce_diag_blocks(p.Nx, p.Ny);
+    hipLaunchKernelGGL(reduce_field_kernel<T>, dim3(nb), dim3(kAuxThreads), 0, s, src, cs, p, phix, phiy, partial);
+    hipLaunchKernelGGL(reduce_field_finish_kernel, dim3(1), dim3(kAuxThreads), 0, s, (const double *)partial, nb,
+                       p.rho0, (double)p.Nx * (double)p.Ny, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_diag_finalize(const double *partial, int nblocks, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(diag_finalize_kernel, dim3(1), dim3(kAuxThreads), 0, s, partial, nblocks, out);
@@ -235,7 +292,9 @@ hipError_t launch_diag_finalize(const double *partial, int nblocks, double *out,
     template hipError_t launch_moments<T>(const T *, double *, double *, double *, bool, const Params<double> &,  \
                                           hipStream_t);                                                           \
     template hipError_t launch_reduce<T>(const T *, bool, const Params<double> &, const DiagArgs<double> &,       \
-                                         hipStream_t);
+                                         hipStream_t);                                                            \
+    template hipError_t launch_reduce_field<T>(const T *, bool, const Params<double> &, const double *,           \
+                                               const double *, double *, double *, hipStream_t);
 
 LB_AUX_INSTANTIATE(float)
 LB_AUX_INSTANTIATE(__half)

@@ -216,6 +216,13 @@ hipError_t launch_moments(const T *src, double *rho, double *ux, double *uy, boo
 template <typename T>
 hipError_t launch_reduce(const T *src, bool cs, const Params<double> &p, const DiagArgs<double> &diag,
                          hipStream_t s);
+// Diagnostics with a full velocity pattern (phix, phiy: [Ny][Nx] FP64 device
+// fields, both NULL for none): {M, Px, Py, E, A} written to out[kDiag]
+// (device) by a second, single-workgroup launch; partial holds
+// (kDiag + 1) * reduce_diag_blocks(Nx, Ny) doubles.
+template <typename T>
+hipError_t launch_reduce_field(const T *src, bool cs, const Params<double> &p, const double *phix, const double *phiy,
+                               double *partial, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_ghosts(T *buf, const Params<double> &p, hipStream_t s);
 int reduce_diag_blocks(int Nx, int Ny);

@@ -20,7 +20,8 @@ Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_F
 
 # every symbol include/lb.h declares (checked by the CPU test-suite)
 EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
-           "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_run_sampled",
+           "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_reduce_field",
+           "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
            "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_rounding_seed", "lb_autotune", "lb_set_tuning",
            "lb_get_tuning", "lb_set_stream", "lb_synchronize",
@@ -56,6 +57,7 @@ def _load():
         "lb_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
         "lb_set_probe": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
         "lb_reduce": (ctypes.c_int, [_vp, _dp]),
+        "lb_reduce_field": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
         "lb_run_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
         "lb_step_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "lb_series_reserve": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -116,8 +118,7 @@ def lb_model_info(model, ds=1.0, dt=1.0):
 
 class Sim:
     """Handle of one simulation: the lb_* calls taking an lb_sim* are its
-    methods (same names without the prefix) and the module-level lb_*
-    functions below."""
+    methods (same names without the prefix)."""
 
     def __init__(self, model, Nx, Ny, tau, dt, ds, N=2, precision=LB_FP32, imex=False):
         self.model, self.Nx, self.Ny, self.N = int(model), int(Nx), int(Ny), int(N)
@@ -177,6 +178,18 @@ class Sim:
     def reduce(self):
         out = np.empty(5)
         _check(_lib.lb_reduce(self._h, _ptr(out)), "lb_reduce")
+        return out
+
+    def reduce_field(self, phi_x=None, phi_y=None):
+        """[M, Px, Py, E, A] with A the projection of u on the pattern
+        (phi_x, phi_y), two [Ny][Nx] fields (None: A = 0)."""
+        out = np.empty(5)
+        if phi_x is None and phi_y is None:
+            _check(_lib.lb_reduce_field(self._h, None, None, _ptr(out)), "lb_reduce_field")
+            return out
+        shp = (self.Ny, self.Nx)
+        px, py = _f64(phi_x, shp), _f64(phi_y, shp)
+        _check(_lib.lb_reduce_field(self._h, _ptr(px), _ptr(py), _ptr(out)), "lb_reduce_field")
         return out
 
     def run_sampled(self, nsteps, every):
@@ -244,100 +257,3 @@ class Sim:
 
     def device_bytes(self):
         return _lib.lb_device_bytes(self._h)
-
-
-# module-level functions with the C names
-def lb_create(model_flags, Nx, Ny, tau, dt, ds, N):
-    return Sim(model_flags & 0xFF, Nx, Ny, tau, dt, ds, N, precision=model_flags & (3 << 8))
-
-
-def lb_destroy(sim):
-    sim.destroy()
-
-
-def lb_set_bc_x(sim, rho_left, rho_right):
-    sim.set_bc_x(rho_left, rho_right)
-
-
-def lb_set_weno_eps(sim, eps):
-    sim.set_weno_eps(eps)
-
-
-def lb_init(sim, rho, ux, uy):
-    sim.init(rho, ux, uy)
-
-
-def lb_step(sim, nsteps=1):
-    sim.step(nsteps)
-
-
-def lb_moments(sim):
-    return sim.moments()
-
-
-def lb_set_probe(sim, ax=None, ay=None, bx=None, by=None):
-    sim.set_probe(ax, ay, bx, by)
-
-
-def lb_reduce(sim):
-    return sim.reduce()
-
-
-def lb_run_sampled(sim, nsteps, every):
-    return sim.run_sampled(nsteps, every)
-
-
-def lb_step_sampled(sim, nsteps, every):
-    sim.step_sampled(nsteps, every)
-
-
-def lb_series_reserve(sim, capacity):
-    sim.series_reserve(capacity)
-
-
-def lb_series_read(sim, max_rows=1 << 16):
-    return sim.series_read(max_rows)
-
-
-def lb_get_state(sim):
-    return sim.get_state()
-
-
-def lb_set_state(sim, f):
-    sim.set_state(f)
-
-
-def lb_steps_done(sim):
-    return sim.steps_done()
-
-
-def lb_set_graph_steps(sim, steps):
-    sim.set_graph_steps(steps)
-
-
-def lb_set_rounding_seed(sim, seed):
-    sim.set_rounding_seed(seed)
-
-
-def lb_autotune(sim, reps=20):
-    return sim.autotune(reps)
-
-
-def lb_set_tuning(sim, cs_threads, fd_rows, fd_rows_rest=None):
-    sim.set_tuning(cs_threads, fd_rows, fd_rows_rest)
-
-
-def lb_get_tuning(sim):
-    return sim.tuning()
-
-
-def lb_set_stream(sim, stream_handle):
-    sim.set_stream(stream_handle)
-
-
-def lb_synchronize(sim):
-    sim.synchronize()
-
-
-def lb_device_bytes(sim):
-    return sim.device_bytes()

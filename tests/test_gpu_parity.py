@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1904_02471_amd import lb, workloads
-from tests.gpu_helpers import PREC_NAME, assert_state_close, pair, tolerance
+from tests.gpu_helpers import PREC_NAME, assert_state_close, field_errors, pair, tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,10 @@ def fd_params(model, Nx):
     return ds, dt, 2.0 * dt
 
 
-def run_and_compare(g, o, steps, prec, what):
+def run_and_compare(g, o, steps, prec, what, fields=False):
+    """Step both sides and compare the states element by element after each
+    count in `steps`; with `fields` (FP32), also rho - rho0 and u against the
+    oracle's within 1e-5 relative L2."""
     done = 0
     for n in steps:
         g.step(n - done)
@@ -34,8 +37,12 @@ def run_and_compare(g, o, steps, prec, what):
         done = n
         fo = o.get_state()
         fg = g.get_state()
-        tol = tolerance(prec, n, fo, g.w, fg.sum(0).mean())
+        tol = tolerance(prec, n, fo, g.w, fo.sum(0).mean())
         assert_state_close(fg, fo, tol, "%s after %d steps" % (what, n))
+        if fields:
+            e_rho, e_u = field_errors(g, o)
+            print("%s after %d steps: rel-L2 rho-rho0 %.2e u %.2e" % (what, n, e_rho, e_u), flush=True)
+            assert e_rho <= 1e-5 and e_u <= 1e-5
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_NAME[p])
@@ -47,7 +54,7 @@ def test_cs_8x8_random_state(prec):
     o.set_state(f0)
     # the state transfer itself is exact up to the storage rounding
     assert_state_close(g.get_state(), f0, tolerance(prec, 0, f0, g.w, f0.sum(0).mean()), "cs set/get state")
-    run_and_compare(g, o, [1, 10, 100], prec, "cs 8x8 " + PREC_NAME[prec])
+    run_and_compare(g, o, [1, 10, 100], prec, "cs 8x8 " + PREC_NAME[prec], fields=prec == lb.LB_FP32)
 
 
 @pytest.mark.parametrize("shape", [(37, 23), (300, 5), (1, 7), (5, 1), (257, 130)])
@@ -109,7 +116,8 @@ def test_fd_8x8_random_state(model, N, prec):
     f0 = workloads.random_distribution(g.K, 8, 8, 11 + model, g.w, spread=0.3)
     g.set_state(f0)
     o.set_state(f0)
-    run_and_compare(g, o, [1, 3, 10], prec, "fd model %d N %d %s" % (model, N, PREC_NAME[prec]))
+    run_and_compare(g, o, [1, 3, 10], prec, "fd model %d N %d %s" % (model, N, PREC_NAME[prec]),
+                    fields=prec == lb.LB_FP32)
 
 
 @pytest.mark.parametrize("model,N", [(lb.LB_FD_D2Q16, 3), (lb.LB_FD_D2Q36, 4), (lb.LB_FD_D2Q9, 2)])
@@ -122,7 +130,7 @@ def test_fd_ragged_tiles(model, N):
     rho, ux, uy = workloads.random_state(Nx, Ny, 3, 1.0, u_max=0.1)
     g.init(rho, ux, uy)
     o.init(rho, ux, uy)
-    run_and_compare(g, o, [1, 4], lb.LB_FP32, "fd %dx%d" % (Nx, Ny))
+    run_and_compare(g, o, [1, 4], lb.LB_FP32, "fd %dx%d" % (Nx, Ny), fields=True)
 
 
 @pytest.mark.parametrize("shape", [(1, 9), (9, 1), (3, 2), (130, 17)])
@@ -314,3 +322,46 @@ def test_step_sampled_series():
     ref = o.run_sampled(10, 5)
     np.testing.assert_allclose(rows[:, 1:], ref, rtol=1e-12, atol=1e-15 * ref[0, 0])
     assert g.series_read().shape == (0, 6)
+
+
+@pytest.mark.parametrize("model", [lb.LB_CS_D2Q9, lb.LB_FD_D2Q16])
+@pytest.mark.parametrize("prec", [lb.LB_FP64, lb.LB_FP32], ids=lambda p: PREC_NAME[p])
+def test_reduce_field(model, prec):
+    """lb_reduce_field: diagnostics with an arbitrary (non-separable) velocity
+    pattern against the oracle's, and with a separable one against lb_reduce
+    (same sums in the same order: M, P, E bitwise, A to rounding)."""
+    Nx, Ny = 70, 45
+    print("case: reduce_field", model, PREC_NAME[prec], flush=True)
+    if model == lb.LB_CS_D2Q9:
+        g, o = cs_case(Nx, Ny, tau=0.6, prec=prec)
+    else:
+        ds, dt, tau = fd_params(model, Nx)
+        g, o = pair(model, Nx, Ny, tau, dt, ds, 3, prec)
+    rho, ux, uy = workloads.random_state(Nx, Ny, 41, g.cs, u_max=0.05)
+    g.init(rho, ux, uy)
+    o.init(rho, ux, uy)
+    g.step(3)
+    o.step(3)
+    rng = np.random.default_rng(1905)
+    px, py = rng.standard_normal((Ny, Nx)), rng.standard_normal((Ny, Nx))
+    dg = g.reduce_field(px, py)
+    do = o.reduce(px, py)
+    tol = 1e-12 if prec == lb.LB_FP64 else 1e-6
+    print("reduce_field gpu", dg, "oracle", do, flush=True)
+    assert dg[0] == pytest.approx(do[0], rel=max(tol, 1e-13))
+    for i in (1, 2):
+        assert abs(dg[i] - do[i]) <= tol * do[0] * 0.05 * g.cs
+    assert dg[3] == pytest.approx(do[3], rel=10 * tol)
+    _, xo, yo = o.moments()
+    a_scale = float(np.sum(np.abs(xo * px) + np.abs(yo * py)) / np.sum(px * px + py * py))
+    assert abs(dg[4] - do[4]) <= 10 * tol * a_scale
+    # no pattern: A = 0, the rest unchanged
+    d0 = g.reduce_field()
+    assert d0[4] == 0.0 and np.array_equal(d0[:4], dg[:4])
+    # a separable pattern through both entry points
+    ax, ay, bx, by = workloads.separable_pattern("tgv", Nx, Ny)
+    g.set_probe(ax, ay, bx, by)
+    dr = g.reduce()
+    df = g.reduce_field(np.outer(ay, ax), np.outer(by, bx))
+    assert np.array_equal(dr[:4], df[:4])
+    assert df[4] == pytest.approx(dr[4], rel=1e-12)
