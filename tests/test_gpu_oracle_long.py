@@ -2,9 +2,9 @@
 vortices (the 512^2 workload's initial state and relaxation time, on grids
 the oracle finishes in seconds) for CS D2Q9, FD D2Q16 (N = 3) and FD D2Q36
 (N = 4).  The target is a relative L2 error of at most 1e-5 in the fields
-after 1000 steps; u is held to it.  rho - rho0 (about 1e-4 of rho) is reported
-beside it and bounded by what the FP32 rounding of the stored populations
-leaves in it (see the test)."""
+after 1000 steps: u and rho are held to it.  rho - rho0 (about 1e-4 of rho)
+is reported beside them and held to what the FP32 rounding of the stored
+populations leaves in it (see the test); it does not reach 1e-5."""
 import math
 import os
 
@@ -56,9 +56,18 @@ def test_tgv_fp32_1000_steps_against_oracle(model, n, N):
     print("1000 steps: rel-L2 u %.2e, rho %.2e, rho - rho0 %.2e (target 1e-5)" % (e_u, e_full, e_rho), flush=True)
     assert e_u <= 1e-5
     assert e_full <= 1e-5
-    # rho - rho0 is ~1e-4 absolute: each stored FP32 population rounds by
-    # ~2^-24 of its shifted value once per step (CS) or stage (FD), ~1e-10
-    # absolute, and the lightly damped sound modes carry it; bound it by that
-    # accumulation over 1000 steps relative to the signal (|rho - rho0| ~ 1e-4)
-    bound = 2.0 ** -24 * math.sqrt(3 * 1000) * 1e3
+    # rho - rho0 (rms ~7.5e-5) carries the rounding of the stored populations:
+    # each rounds by up to 2^-24 of its shifted value (|g| up to ~5e-3, the
+    # momentum-carrying part) once per step (CS) or stage (FD); the density
+    # sums K of them, and R = 1000 (CS) or 3000 (FD) independent roundings
+    # accumulate like a random walk (no credit for the damping of the sound
+    # modes that carry them): |d rho| ~ 2^-24 max|g| sqrt(K R)
+    f = o.get_state()
+    K = f.shape[0]
+    vx, vy, w = o.velocities()
+    r0 = float(ro.mean())
+    gmax = float(np.max(np.abs(f - w[:, None, None] * r0)))
+    R = 1000 if model == lb.LB_CS_D2Q9 else 3000
+    bound = 2.0 ** -24 * gmax * math.sqrt(K * R) / float(np.sqrt(np.mean((ro - r0) ** 2)))
+    print("rho - rho0: rel-L2 %.2e, rounding-noise bound %.2e" % (e_rho, bound), flush=True)
     assert e_rho <= bound
