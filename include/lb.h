@@ -169,6 +169,29 @@ int lb_reduce(lb_sim *sim, double out[5]);
  * not finite; LB_ENAN when a result is not finite. */
 int lb_reduce_field(lb_sim *sim, const double *phi_x, const double *phi_y, double out[5]);
 
+/* lb_reduce_field for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same results, bit for bit, with the pattern and the
+ * output in caller-owned DEVICE memory and nothing allocated or
+ * synchronised.
+ *   d_phi_x, d_phi_y: device arrays [Ny][Nx] of doubles (both NULL: A = 0),
+ *     read by kernels on the handle's stream: they must be ready on that
+ *     stream and stay valid until the call's work has run.
+ *   d_out: device array of 5 doubles, written on the handle's stream
+ *     {M, Px, Py, E, A} as lb_reduce_field computes them.
+ * Enqueued asynchronously on the handle's stream; no non-finite check (read
+ * d_out after a synchronisation).  Per-block partial sums go to one fixed
+ * device array per GPU, held until the process ends: (5 + 1) doubles for
+ * each of at most 1024 blocks (48 KiB), which every grid lb_create accepts
+ * fits (a larger need returns LB_EINVAL).  Every call on a GPU shares that
+ * GPU's array and leaves its partials there (each call writes all it reads,
+ * so nothing needs clearing): calls that overlap on one GPU, on different
+ * streams or from different threads, race and must be serialised by the
+ * caller.  Switches to the handle's device for the call if another is
+ * current.  LB_EINVAL if only one of the pattern pointers is given or d_out
+ * is NULL, LB_ESTATE before lb_init / lb_set_state. */
+int lb_reduce_field_noalloc(lb_sim *sim, const double *d_phi_x, const double *d_phi_y, double *d_out);
+
 /* Advance nsteps steps; for every step whose input state has
  * lb_steps_done() % every == 0, the diagnostics of that input state are
  * computed inside the step kernels (no extra pass over the state) and

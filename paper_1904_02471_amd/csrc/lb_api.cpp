@@ -452,6 +452,12 @@ lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double
         fail(LB_ENOMEM);
         return nullptr;
     }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        fail(LB_EDEVICE);
+        return nullptr;
+    }
     s->model = model;
     s->imex = (model_flags & LB_IMEX) != 0;
     s->prec = precbits == LB_FP16_SHIFTED ? P16 : (precbits == LB_FP64 ? P64 : P32);
@@ -903,6 +909,33 @@ int lb_reduce_field(lb_sim *s, const double *phi_x, const double *phi_y, double 
     if (e != hipSuccess) return fail(dev_status(e));
     if (!all_finite(out, kDiag)) return fail(LB_ENAN);
     return LB_OK;
+}
+
+int lb_reduce_field_noalloc(lb_sim *s, const double *d_phi_x, const double *d_phi_y, double *d_out)
+{
+    if (!s || !d_out || (!d_phi_x) != (!d_phi_y)) return fail(LB_EINVAL);
+    if (!s->ready) return fail(LB_ESTATE);
+    // the per-block partials live in the library's fixed device array of the
+    // simulation's device (reduce_field_scratch), not in allocated memory
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(LB_EDEVICE);
+    if (cur != s->device && hipSetDevice(s->device) != hipSuccess) return fail(LB_EDEVICE);
+    double *scratch = nullptr;
+    size_t cap = 0;
+    hipError_t e = reduce_field_scratch(s->device, &scratch, &cap);
+    int rc = dev_status(e);
+    if (rc == LB_OK && (size_t)(kDiag + 1) * (size_t)reduce_diag_blocks(s->Nx, s->Ny) > cap) rc = LB_EINVAL;
+    if (rc == LB_OK) {
+        const Params<double> p = make_params<double>(s);
+        e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return launch_reduce_field<T>(bufp<T>(s, state_index(s)), s->cs, p, d_phi_x, d_phi_y, scratch, d_out,
+                                          s->stream);
+        });
+        rc = dev_status(e);
+    }
+    if (cur != s->device) (void)hipSetDevice(cur);
+    return rc == LB_OK ? LB_OK : fail(rc);
 }
 
 int lb_series_reserve(lb_sim *s, int capacity)

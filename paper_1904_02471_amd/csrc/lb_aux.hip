@@ -7,6 +7,8 @@
 // node, so the canonical (pre-collision) value f_k(x) is read from x - e_k
 // ("pull") and written to x - e_k ("push").  Finite-difference storage holds
 // f_k(x) at x.
+#include <mutex>
+
 #include "lb_diag.h"
 #include "lb_internal.h"
 
@@ -16,6 +18,11 @@ namespace {
 
 constexpr int kAuxThreads = 256;
 constexpr int kReduceMaxBlocks = 1024;
+
+constexpr size_t kScratchDoubles = (size_t)(kDiag + 1) * kReduceMaxBlocks;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
 
 __device__ __forceinline__ int wrapi(int v, int n)
 {
@@ -208,6 +215,30 @@ __global__ __launch_bounds__(kAuxThreads) void reduce_field_finish_kernel(const 
 unsigned grid_for(long long n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
 
 }  // namespace
+
+// Per-block partials of the field reduction for callers that cannot allocate
+// (lb_reduce_field_noalloc): a fixed array of (kDiag + 1) doubles for each of
+// the at most kReduceMaxBlocks blocks (48 KiB), one copy per GPU for the
+// life of the process.  Host code never passes `scratch` itself (in host
+// code the name is a stand-in, not a device address): it passes the
+// address hipGetSymbolAddress returned for the device.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t reduce_field_scratch(int device, double **ptr, size_t *capacity)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        // the caller has made `device` current
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    *capacity = kScratchDoubles;
+    return hipSuccess;
+}
 
 int reduce_diag_blocks(int Nx, int Ny)
 {

@@ -223,6 +223,9 @@ hipError_t launch_reduce(const T *src, bool cs, const Params<double> &p, const D
 template <typename T>
 hipError_t launch_reduce_field(const T *src, bool cs, const Params<double> &p, const double *phix, const double *phiy,
                                double *partial, double *out, hipStream_t s);
+// Device address and capacity (doubles) of the fixed partials array of the
+// field reduction on `device` (looked up once per device; thread-safe).
+hipError_t reduce_field_scratch(int device, double **ptr, size_t *capacity);
 template <typename T>
 hipError_t launch_fill_ghosts(T *buf, const Params<double> &p, hipStream_t s);
 int reduce_diag_blocks(int Nx, int Ny);

@@ -15,6 +15,7 @@ enum Prec { P32 = 0, P16 = 1, P64 = 2 };
 }  // namespace lbm
 
 struct lb_sim {
+    int device = 0;  // HIP device current at lb_create, which holds the buffers
     int model = 0;
     lbm::Prec prec = lbm::P32;
     bool cs = true;

@@ -21,6 +21,7 @@ Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_F
 # every symbol include/lb.h declares (checked by the CPU test-suite)
 EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_info", "lb_set_bc_x",
            "lb_set_weno_eps", "lb_init", "lb_step", "lb_moments", "lb_set_probe", "lb_reduce", "lb_reduce_field",
+           "lb_reduce_field_noalloc",
            "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
            "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_rounding_seed", "lb_autotune", "lb_set_tuning",
@@ -58,6 +59,7 @@ def _load():
         "lb_set_probe": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
         "lb_reduce": (ctypes.c_int, [_vp, _dp]),
         "lb_reduce_field": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+        "lb_reduce_field_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
         "lb_run_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp]),
         "lb_step_sampled": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "lb_series_reserve": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -191,6 +193,14 @@ class Sim:
         px, py = _f64(phi_x, shp), _f64(phi_y, shp)
         _check(_lib.lb_reduce_field(self._h, _ptr(px), _ptr(py), _ptr(out)), "lb_reduce_field")
         return out
+
+    def reduce_field_noalloc(self, d_phi_x, d_phi_y, d_out):
+        """lb_reduce_field_noalloc: device pointers (integers, 0 / None for no
+        pattern) of the two [Ny][Nx] FP64 pattern fields and of the 5-double
+        output; enqueued on the handle's stream, nothing allocated."""
+        _check(_lib.lb_reduce_field_noalloc(self._h, ctypes.c_void_p(int(d_phi_x or 0)),
+                                            ctypes.c_void_p(int(d_phi_y or 0)), ctypes.c_void_p(int(d_out or 0))),
+               "lb_reduce_field_noalloc")
 
     def run_sampled(self, nsteps, every):
         n = int(nsteps) // int(every) + 1 if int(every) > 0 and int(nsteps) >= 0 else 1
