@@ -63,7 +63,7 @@ def parse():
                     help="time one model alone (profiling runs); the JSON line is then per model")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of the CS state size (counter calibration)")
-    ap.add_argument("--serving-requests", type=int, default=128,
+    ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving stream to replay (0: skip; 512: the whole stream)")
     return ap.parse_args()
 
@@ -112,10 +112,11 @@ def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
             b.record(stream)
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
-        gbs = 2 * 9 * s * n * n / (ms * 1e-3) / 1e9
+        bpn = 18 * s
+        gbs = bpn * n * n / (ms * 1e-3) / 1e9
         out[name] = {"ms_per_step": round(ms, 5), "mlups": round(n * n / (ms * 1e-3) / 1e6, 1),
                      "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "bytes_per_node_step": 18 * s, "cs_threads": threads}
+                     "bytes_per_node_step": bpn, "cs_threads": threads}
         sim.destroy()
     return out
 
@@ -241,13 +242,31 @@ def cpu_baseline(every, n):
                                         "512x512 x 2 steps (%.4f MLUPS)" % (1e-6 / s_cs, 1e-6 / s_fd)}}
 
 
+def decay_fit_args(entry, kw):
+    """(decay_k2, omega) of a serving request's viscosity fit: the amplitude
+    of a shear wave decays at nu k^2, of a Taylor-Green vortex at 2 nu k^2
+    (k = 2 pi / side per lattice spacing for CS, 2 pi on the FD unit box);
+    a vortex started from f = f_eq rings at omega = 2 k c_s, fitted along when
+    the run spans at least two periods."""
+    from paper_1904_02471_amd import lb
+    cs_model = kw["model"] == lb.LB_CS_D2Q9
+    k = 2 * math.pi / entry["side"] if cs_model else 2 * math.pi
+    if entry["kind"] == "shear":
+        return k * k, 0.0
+    omega = 2 * k * (1 / math.sqrt(3) if cs_model else 1.0)
+    return 2 * k * k, (omega if omega * kw["nsteps"] * kw["dt"] >= 4 * math.pi else 0.0)
+
+
 def serving_bench(n_requests, every):
     """Replay the first n_requests of the seeded serving stream (Poisson
     arrivals, mean gap 2 ms; square grids 64..1024; CS D2Q9 or FD D2Q16;
     500-5000 steps) twice on the GPU: batched (lb_server, continuous
-    batching) and one simulation per launch sequence (lb_sim per request, in
-    arrival order).  Reports sims/s and p50/p99 time-to-result (completion
-    minus arrival) for both, and whether every result is identical."""
+    batching: batched launches replayed as captured graphs, admission on a
+    second stream) and one simulation per launch sequence (lb_sim per
+    request, in arrival order, each alone on the GPU).  Reports sims/s,
+    p50/p99 time-to-result (completion minus arrival) and service time
+    (completion minus admission), and each request's apparent viscosity (the
+    library's FP64 fit of its amplitude series) alone and in the mix."""
     import numpy as np
 
     from paper_1904_02471_amd import lb, serve, workloads
@@ -255,6 +274,7 @@ def serving_bench(n_requests, every):
     trace = workloads.serving_trace(n_requests, 1904)
     fields = serve.field_cache()
     reqs = [serve.trace_request(e, fields) for e in trace]
+    fits = [decay_fit_args(e, kw) for e, kw in zip(trace, reqs)]
     n = len(trace)
 
     # batched, continuous admission
@@ -266,7 +286,7 @@ def serving_bench(n_requests, every):
     while len(results) < n:
         now = time.perf_counter() - t0
         while k < n and trace[k]["arrival_s"] <= now:
-            srv.submit(sample_every=every, tag=k, **reqs[k])
+            srv.submit(sample_every=every, tag=k, decay_k2=fits[k][0], decay_omega=fits[k][1], **reqs[k])
             k += 1
         for r in srv.poll(256, 500):
             results[r["tag"]] = r
@@ -277,15 +297,19 @@ def serving_bench(n_requests, every):
     stats = srv.stats()
     srv.close()
     lat_b = np.array([results[i]["t_finish"] - (c0 + trace[i]["arrival_s"]) for i in range(n)])
+    svc_b = np.array([results[i]["t_finish"] - results[i]["t_admit"] for i in range(n)])
     assert all(results[i]["status"] == 0 for i in range(n))
 
     # one simulation per launch sequence
     lat_s = np.zeros(n)
+    svc_s = np.zeros(n)
+    nu_alone = np.zeros(n)
     same = True
     t0 = time.perf_counter()
     for i, e in enumerate(trace):
         while time.perf_counter() - t0 < e["arrival_s"]:
             time.sleep(2e-4)
+        ts = time.perf_counter()
         kw = reqs[i]
         g = lb.Sim(kw["model"], kw["Nx"], kw["Ny"], kw["tau"], kw["dt"], kw["ds"], kw["N"], precision=lb.LB_FP32)
         g.init(kw["rho"], kw["ux"], kw["uy"])
@@ -296,25 +320,42 @@ def serving_bench(n_requests, every):
         fin = np.concatenate([[kw["nsteps"]], g.reduce()])
         g.destroy()
         lat_s[i] = time.perf_counter() - t0 - e["arrival_s"]
-        same = same and np.array_equal(np.vstack([rows, fin]), results[i]["samples"])
+        svc_s[i] = time.perf_counter() - ts
+        series = np.vstack([rows, fin])
+        same = same and np.array_equal(series, results[i]["samples"])
+        nu_alone[i] = serve.fit_decay(series[:, 0] * kw["dt"], series[:, 5], fits[i][1]) / fits[i][0]
         if (i + 1) % 64 == 0:
             print("serving one-by-one: %d/%d done at %.1f s" % (i + 1, n, time.perf_counter() - t0),
                   file=sys.stderr, flush=True)
     wall_s = time.perf_counter() - t0
     nodes_steps = sum(kw["Nx"] * kw["Ny"] * kw["nsteps"] for kw in reqs)
+    nu_mix = np.array([results[i]["nu_app"] for i in range(n)])
+    # viscosity each request was set up with: CS nu = (tau - 1/2)/3 in
+    # lattice units, FD nu = tau_FD on the unit box
+    nu0 = np.array([(kw["tau"] - 0.5) / 3.0 if kw["model"] == lb.LB_CS_D2Q9 else kw["tau"] for kw in reqs])
+    err = np.abs(nu_mix / nu0 - 1)
+
+    def pct(a, q):
+        return round(float(np.percentile(a, q)), 4)
     return {
         "requests": n, "stream": "seed 1904, Poisson arrivals mean 2 ms, side U{64..1024}, CS D2Q9 / FD D2Q16 "
                                   "50/50, tau U[0.55,1.5], steps U{500..5000}, FP32, diagnostics every %d" % every,
         "batched": {"sims_per_s": round(n / wall_b, 3), "wall_s": round(wall_b, 3),
-                    "p50_s": round(float(np.percentile(lat_b, 50)), 4),
-                    "p99_s": round(float(np.percentile(lat_b, 99)), 4),
+                    "p50_s": pct(lat_b, 50), "p99_s": pct(lat_b, 99),
+                    "service_p50_s": pct(svc_b, 50), "service_p99_s": pct(svc_b, 99),
                     "mlups": round(nodes_steps / wall_b / 1e6, 1), "batch_steps": stats["batch_steps"]},
         "one_sim_per_launch": {"sims_per_s": round(n / wall_s, 3), "wall_s": round(wall_s, 3),
-                               "p50_s": round(float(np.percentile(lat_s, 50)), 4),
-                               "p99_s": round(float(np.percentile(lat_s, 99)), 4),
+                               "p50_s": pct(lat_s, 50), "p99_s": pct(lat_s, 99),
+                               "service_p50_s": pct(svc_s, 50), "service_p99_s": pct(svc_s, 99),
                                "mlups": round(nodes_steps / wall_s / 1e6, 1)},
         "speedup_sims_per_s": round(wall_s / wall_b, 3),
         "results_identical": bool(same),
+        "nu_app": {"fit": "FP64 least squares of ln A(t) (lb_fit_decay) over every sample; Taylor-Green runs "
+                          "spanning two acoustic periods fit the ringing at 2 k c_s along",
+                   "max_rel_diff_alone_vs_mix": float(np.max(np.abs(nu_mix / nu_alone - 1))),
+                   "rel_err_vs_setup_nu_p50": float(np.percentile(err, 50)),
+                   "rel_err_vs_setup_nu_p99": float(np.percentile(err, 99)),
+                   "rel_err_vs_setup_nu_max": float(np.max(err))},
     }
 
 

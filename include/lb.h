@@ -275,18 +275,25 @@ size_t lb_device_bytes(const lb_sim *sim);
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of many independent simulations.
  *
- * A server owns one HIP stream and a worker thread.  Submitted requests wait
- * in a queue; the worker admits them while the device-memory budget and the
- * slot count allow (footprint = state buffers + diagnostics of the
- * simulation), initialises them, and advances every admitted simulation by
- * one step per batched launch (one launch for all collision-streaming
- * simulations, three stage launches per equilibrium order for the
- * finite-difference ones).  Requests that arrive while others run are
- * admitted between chunks of batched steps as memory frees up; a finished
- * simulation is drained (final diagnostics), its memory released and its
- * result queued for lb_server_poll.  Each simulation computes the same
- * values as a single lb_sim run of the same request (same per-row / per-tile
- * device code), whatever else shares the batch.
+ * A server owns a compute stream, an admission stream (same priority) and a
+ * worker thread (started by the first lb_server_submit).  Submitted requests
+ * wait in a queue; the worker admits them while the device-memory budget and
+ * the slot count allow (footprint = state buffers + diagnostics of the
+ * simulation), creating and initialising them on the admission stream while
+ * the batched steps of the running simulations proceed on the compute
+ * stream.  Every admitted simulation advances by one step per batched step:
+ * one launch for all collision-streaming simulations, three Runge-Kutta stage
+ * launches per equilibrium order for the finite-difference ones, one launch
+ * for the sampled diagnostics; a batched step of a given running set is
+ * captured once as a HIP graph and replayed (the kernels read the step index
+ * from device memory).  Runs of batched steps ("chunks") end at the first
+ * completion or after chunk_steps steps; between chunks the finished
+ * simulations are drained (final diagnostics, apparent viscosity), their
+ * memory is released and the newly admitted ones join.  The later-stage FD
+ * tile height (64 x 16 or 64 x 32) is chosen per equilibrium order by timing
+ * both on the first running set that has the order.  Each simulation
+ * computes the same values as a single lb_sim run of the same request (same
+ * per-row / per-tile device code), whatever else shares the batch.
  * Supported requests: periodic, FP32 storage, any model.
  * ------------------------------------------------------------------------ */
 typedef struct lb_server lb_server;
@@ -302,6 +309,11 @@ typedef struct lb_request {
     int nsteps;               /* steps to run, >= 1 */
     int sample_every;         /* diagnostics every this many steps, >= 1 */
     uint64_t tag;             /* returned in the result */
+    double decay_k2;          /* > 0 (needs a probe): fit the amplitude series A(t), t = step dt, and
+                                 return nu_app = decay rate / decay_k2 (shear wave of wavenumber k:
+                                 k^2, Section 4.2; Taylor-Green vortex: 2 k^2, Section 4.3); 0: no fit */
+    double decay_omega;       /* >= 0: angular frequency (per unit of t) of a modulation fitted along
+                                 (lb_fit_decay), 0 for none */
 } lb_request;
 
 typedef struct lb_result {
@@ -312,12 +324,22 @@ typedef struct lb_result {
                                  t = 0, every, 2 every, ... < nsteps and the final state
                                  t = nsteps; owned by the server until lb_server_release */
     double t_submit, t_admit, t_finish;  /* seconds on the server clock */
+    double nu_app;            /* apparent viscosity of the request's fit (NaN without one, or when the
+                                 fit fails) */
 } lb_result;
 
 /* hbm_budget_bytes: device memory the admitted simulations may hold;
  * max_slots: simulations admitted at once (1..4096); chunk_steps: batched
  * steps between admission / drain points (>= 1).  NULL on error. */
 lb_server *lb_server_create(size_t hbm_budget_bytes, int max_slots, int chunk_steps);
+
+/* Launch options, before the first lb_server_submit (LB_ESTATE after it):
+ * use_graphs 1 (default) replays each batched step as a captured HIP graph,
+ * 0 launches its kernels one by one (the same kernels in the same order:
+ * the results are bitwise the same); tune_tiles 1 (default) times the FD
+ * later-stage tile heights per order, 0 keeps 64 x 16.  LB_EINVAL for values
+ * other than 0 and 1. */
+int lb_server_configure(lb_server *srv, int use_graphs, int tune_tiles);
 
 /* Queue a request (non-blocking).  LB_EINVAL for a request that lb_create
  * would reject or that is not supported in a batch; LB_EBUSY when the
@@ -342,6 +364,17 @@ int lb_server_stats(const lb_server *srv, double out[7]);
 /* Stop the worker (running and queued requests are abandoned) and release
  * every resource.  NULL is ignored. */
 void lb_server_destroy(lb_server *srv);
+
+/* Decay rate of an amplitude series, the FP64 viscosity fit of Sections
+ * 4.2-4.3 (a shear wave decays as exp(-nu k^2 t), a Taylor-Green vortex as
+ * exp(-2 nu k^2 t); the paper does not state its fit): least squares of
+ * ln|amp[i]| on {1, -t[i]}, or with omega > 0 on {1, -t[i], cos(omega t[i]),
+ * sin(omega t[i])} (a modulation at a known frequency fitted along, e.g. the
+ * standing sound wave of a vortex started from the incompressible pressure).
+ * t, amp: n host values; *rate receives the coefficient of -t.  LB_EINVAL for
+ * n below 3 (5 with omega), a zero or non-finite value, or a degenerate
+ * design; LB_ENAN for a non-finite result. */
+int lb_fit_decay(const double *t, const double *amp, int n, double omega, double *rate);
 
 #ifdef __cplusplus
 }

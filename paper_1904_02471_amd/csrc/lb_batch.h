@@ -25,21 +25,28 @@ struct BatchSlot {
 
 // One workgroup of a batched launch: simulation `slot`, row (CS) or tile
 // (FD) `local`.  FD tiles are 64 x 32 nodes in the first Runge-Kutta stage
-// (the canonical tiles of the fused diagnostics) and 64 x kFdLaterTileRows
-// in the later stages; a stage's output does not depend on the tile shape.
-constexpr int kFdLaterTileRows = 16;
+// (the canonical tiles of the fused diagnostics) and 64 x 16 or 64 x 32 in
+// the later stages (a tuning choice per equilibrium order); a stage's
+// output does not depend on the tile shape.
 struct BatchWork {
     int slot, local;
 };
 
-// A simulation steps in the launch of batch step `epoch` while
-// 0 <= epoch - start_epoch < nsteps; its own step index selects the
-// ping-pong buffers and whether the input state is sampled.
-hipError_t launch_cs_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int epoch, hipStream_t s);
-hipError_t launch_fd_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int N, int stage, int epoch,
+// The batch step ("epoch") is read from device memory (*epoch), so that a
+// captured launch sequence replays unchanged from step to step; a
+// simulation steps in a launch while 0 <= epoch - start_epoch < nsteps, and
+// its own step index selects the ping-pong buffers and whether the input
+// state is sampled.  launch_epoch_advance adds one to *epoch after the
+// launches of a step.
+hipError_t launch_cs_batch(const BatchSlot *slots, const BatchWork *work, int nwork, const int *epoch,
                            hipStream_t s);
-// Sums the partials of every listed simulation that sampled in `epoch`
+// stage 1 on 64 x 32 tiles; stages 2 and 3 on 64 x (4 rows) tiles, rows 4 or 8
+hipError_t launch_fd_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int N, int stage, int rows,
+                           const int *epoch, hipStream_t s);
+// Sums the partials of every listed simulation that sampled in this epoch
 // into its series.
-hipError_t launch_finalize_batch(const BatchSlot *slots, const int *slot_ids, int nslots, int epoch, hipStream_t s);
+hipError_t launch_finalize_batch(const BatchSlot *slots, const int *slot_ids, int nslots, const int *epoch,
+                                 hipStream_t s);
+hipError_t launch_epoch_advance(int *epoch, hipStream_t s);
 
 }  // namespace lbm

@@ -1,8 +1,10 @@
 // lb_batch.hip -- batched kernels of the serving form: one launch steps all
 // admitted simulations of a kind together, each workgroup taking one row
 // (collision-streaming) or one tile (finite-difference: 64 x 32 in the first
-// stage, 64 x 16 in the later ones) of one simulation from a work list.  The per-row / per-tile device code is the
-// same as in the single-simulation kernels (lb_cs_impl.h, lb_fd_impl.h).
+// stage, 64 x 16 or 64 x 32 in the later ones) of one simulation from a work
+// list.  The per-row / per-tile device code is the same as in the
+// single-simulation kernels (lb_cs_impl.h, lb_fd_impl.h).  The batch step is
+// read from device memory, so that a captured step replays unchanged.
 #include "lb_batch.h"
 #include "lb_cs_impl.h"
 #include "lb_fd_impl.h"
@@ -14,8 +16,10 @@ namespace {
 __device__ __forceinline__ int step_of(const BatchSlot &s, int epoch) { return epoch - s.start_epoch; }
 
 __global__ __launch_bounds__(kCsThreads) void cs_batch_kernel(const BatchSlot *__restrict__ slots,
-                                                              const BatchWork *__restrict__ work, int epoch)
+                                                              const BatchWork *__restrict__ work,
+                                                              const int *__restrict__ epoch_ptr)
 {
+    const int epoch = *epoch_ptr;
     const BatchWork w = work[blockIdx.x];
     const BatchSlot &s = slots[w.slot];
     const int e = step_of(s, epoch);
@@ -40,11 +44,12 @@ __global__ __launch_bounds__(kCsThreads) void cs_batch_kernel(const BatchSlot *_
     }
 }
 
-template <int N, int STAGE>
+template <int N, int STAGE, int ROWS>
 __global__ __launch_bounds__(kFdThreads) void fd_batch_kernel(const BatchSlot *__restrict__ slots,
-                                                              const BatchWork *__restrict__ work, int epoch,
-                                                              float cb)
+                                                              const BatchWork *__restrict__ work,
+                                                              const int *__restrict__ epoch_ptr, float cb)
 {
+    const int epoch = *epoch_ptr;
     // contiguous runs of the work list per XCD (workgroup b runs on XCD b % 8)
     const int nb = gridDim.x, b = blockIdx.x, q = nb / 8, r = nb % 8, x = b % 8;
     const BatchWork w = work[x * q + (x < r ? x : r) + b / 8];
@@ -60,63 +65,80 @@ __global__ __launch_bounds__(kFdThreads) void fd_batch_kernel(const BatchSlot *_
         const DiagArgs<float> d{};
         const float *src = STAGE == 2 ? s.buf[1] : s.buf[2];
         float *out = STAGE == 2 ? s.buf[2] : s.buf[0];
-        static_assert(FdGeom<kFdLaterTileRows / 4>::kTY == kFdLaterTileRows, "later-stage tile height");
-        fd_stage_tile<float, N, false, true, kFdLaterTileRows / 4>(src, s.buf[0], out, cb, s.p, d, bx, by, w.local,
-                                                                   false);
+        fd_stage_tile<float, N, false, true, ROWS>(src, s.buf[0], out, cb, s.p, d, bx, by, w.local, false);
     }
 }
 
 __global__ __launch_bounds__(256) void finalize_batch_kernel(const BatchSlot *__restrict__ slots,
-                                                             const int *__restrict__ ids, int epoch)
+                                                             const int *__restrict__ ids,
+                                                             const int *__restrict__ epoch_ptr)
 {
+    const int epoch = *epoch_ptr;
     const BatchSlot &s = slots[ids[blockIdx.x]];
     const int e = step_of(s, epoch);
     if (e < 0 || e >= s.nsteps || e % s.every != 0) return;
     diag_finalize_block(s.partial, s.diag_blocks, s.series + (long long)(e / s.every) * kDiag);
 }
 
+// after the launches of one batch step (one thread; stream order places it
+// after them)
+__global__ void epoch_advance_kernel(int *epoch) { *epoch += 1; }
+
 template <int N>
-hipError_t launch_fd_n_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int stage, int epoch,
-                             hipStream_t s)
+hipError_t launch_fd_n_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int stage, int rows,
+                             const int *epoch, hipStream_t s)
 {
     // the same stage weights as the single-simulation launcher
     const float cb = stage == 1 ? 1.0f : (stage == 2 ? 0.25f : 2.0f / 3.0f);
     if (stage == 1)
-        hipLaunchKernelGGL((fd_batch_kernel<N, 1>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
+        hipLaunchKernelGGL((fd_batch_kernel<N, 1, kFdRows>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch,
+                           cb);
+    else if (stage == 2 && rows == 4)
+        hipLaunchKernelGGL((fd_batch_kernel<N, 2, 4>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
     else if (stage == 2)
-        hipLaunchKernelGGL((fd_batch_kernel<N, 2>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
+        hipLaunchKernelGGL((fd_batch_kernel<N, 2, 8>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
+    else if (rows == 4)
+        hipLaunchKernelGGL((fd_batch_kernel<N, 3, 4>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
     else
-        hipLaunchKernelGGL((fd_batch_kernel<N, 3>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
+        hipLaunchKernelGGL((fd_batch_kernel<N, 3, 8>), dim3(nwork), dim3(kFdThreads), 0, s, slots, work, epoch, cb);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_cs_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int epoch, hipStream_t s)
+hipError_t launch_cs_batch(const BatchSlot *slots, const BatchWork *work, int nwork, const int *epoch, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     hipLaunchKernelGGL(cs_batch_kernel, dim3(nwork), dim3(kCsThreads), 0, s, slots, work, epoch);
     return hipGetLastError();
 }
 
-hipError_t launch_fd_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int N, int stage, int epoch,
-                           hipStream_t s)
+hipError_t launch_fd_batch(const BatchSlot *slots, const BatchWork *work, int nwork, int N, int stage, int rows,
+                           const int *epoch, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
+    if (rows != 4 && rows != 8) return hipErrorInvalidValue;
     switch (N) {
-    case 1: return launch_fd_n_batch<1>(slots, work, nwork, stage, epoch, s);
-    case 2: return launch_fd_n_batch<2>(slots, work, nwork, stage, epoch, s);
-    case 3: return launch_fd_n_batch<3>(slots, work, nwork, stage, epoch, s);
-    case 4: return launch_fd_n_batch<4>(slots, work, nwork, stage, epoch, s);
-    case 5: return launch_fd_n_batch<5>(slots, work, nwork, stage, epoch, s);
+    case 1: return launch_fd_n_batch<1>(slots, work, nwork, stage, rows, epoch, s);
+    case 2: return launch_fd_n_batch<2>(slots, work, nwork, stage, rows, epoch, s);
+    case 3: return launch_fd_n_batch<3>(slots, work, nwork, stage, rows, epoch, s);
+    case 4: return launch_fd_n_batch<4>(slots, work, nwork, stage, rows, epoch, s);
+    case 5: return launch_fd_n_batch<5>(slots, work, nwork, stage, rows, epoch, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_finalize_batch(const BatchSlot *slots, const int *slot_ids, int nslots, int epoch, hipStream_t s)
+hipError_t launch_finalize_batch(const BatchSlot *slots, const int *slot_ids, int nslots, const int *epoch,
+                                 hipStream_t s)
 {
     if (nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_batch_kernel, dim3(nslots), dim3(256), 0, s, slots, slot_ids, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_epoch_advance(int *epoch, hipStream_t s)
+{
+    hipLaunchKernelGGL(epoch_advance_kernel, dim3(1), dim3(1), 0, s, epoch);
     return hipGetLastError();
 }
 

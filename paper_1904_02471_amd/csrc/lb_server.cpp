@@ -1,20 +1,27 @@
 // lb_server.cpp -- continuous batching of independent simulations (the
 // lb_server_* part of include/lb.h).
 //
-// A worker thread owns the device side.  It loops:
+// A worker thread owns the device side: a compute stream for the batched
+// steps and an admission stream (same priority) for setting up new
+// simulations.  It loops:
 //   1. admit queued requests (FIFO) while the slot count and the device-memory
-//      budget allow: create the simulation, upload and initialise its state;
-//   2. when the set of running simulations changed, rebuild the batch
-//      descriptors and the per-launch work lists (one entry per CS row or
-//      FD tile of every running simulation) and upload them;
-//   3. run a chunk of batched steps: per step one collision-streaming launch,
-//      three stage launches per finite-difference equilibrium order, and one
-//      launch that sums the diagnostics of the simulations sampled in that
-//      step; the chunk ends at the first completion (or after chunk_steps);
-//   4. drain the finished simulations: final diagnostics, series copied to
-//      the host, device memory released, result queued.
-// Requests that arrive meanwhile wait in the queue and are admitted at the
-// next chunk boundary, so new work overlaps with running work on the device.
+//      budget allow: create the simulation, upload and initialise its state on
+//      the admission stream -- while the chunk launched last (if any) still
+//      runs on the compute stream;
+//   2. wait for that chunk; drain the simulations it finished (final
+//      diagnostics, series copied to the host, apparent viscosity fitted,
+//      device memory released, result queued);
+//   3. when the set of running simulations changed, rebuild the batch
+//      descriptors and the work lists (one entry per CS row or FD tile of
+//      every running simulation) and capture one batched step as a HIP graph:
+//      one collision-streaming launch, three stage launches per
+//      finite-difference equilibrium order, one launch that sums the
+//      diagnostics of the simulations sampled in that step, and one that
+//      advances the device-side step counter the kernels read;
+//   4. launch the next chunk, the step graph replayed once per step; the chunk
+//      ends at the first completion (or after chunk_steps).
+// Requests that arrive meanwhile wait in the queue and are admitted while the
+// next chunk runs, so new work overlaps with running work on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,6 +60,7 @@ struct Running {
     double t_submit, t_admit;
     size_t footprint;
     int N;  // FD equilibrium order (0 for CS)
+    double dt, decay_k2, decay_omega;  // viscosity fit of the amplitude series (decay_k2 > 0)
 };
 
 // Device bytes a request will hold: state buffers, diagnostics partials and
@@ -110,6 +118,8 @@ struct lb_server {
     int max_slots = 0;
     int chunk = 0;
     int device = 0;
+    bool use_graphs = true;  // replay each batched step as a captured graph
+    bool tune_tiles = true;  // time the later-stage tile heights per FD order
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -117,22 +127,30 @@ struct lb_server {
     std::deque<Pending> queue;
     std::deque<lb_result> done;
     std::atomic<bool> stop{false};
+    std::atomic<bool> started{false};
     std::thread worker;
 
     // worker-owned state
     std::vector<Running> running;
     size_t used = 0;
-    hipStream_t stream = nullptr;
-    int epoch = 0;
+    hipStream_t stream = nullptr;   // batched steps
+    hipStream_t astream = nullptr;  // admission: create and initialise new simulations
+    hipEvent_t chunk_done = nullptr;
+    bool in_flight = false;         // a chunk was launched and not yet waited for
+    int epoch = 0;                  // batch steps launched (host mirror of *d_epoch)
+    int *d_epoch = nullptr;
     DevArray<BatchSlot> d_slots;
     DevArray<BatchWork> d_cs;
-    // FD work lists per equilibrium order: 64 x 32 tiles for the first
-    // Runge-Kutta stage (the canonical tiles of the fused diagnostics),
-    // 64 x 16 tiles for the later stages (more waves per SIMD)
+    // FD work lists per equilibrium order: 64 x 32 tiles (the first
+    // Runge-Kutta stage, whose tiles index the fused diagnostics) and 64 x 16
+    // tiles; the later stages take the list of the tile height chosen for
+    // their order (rows per thread 4: 64 x 16, 8: 64 x 32)
     std::map<int, DevArray<BatchWork>> d_fd, d_fd16;
     std::map<int, int> n_fd, n_fd16;
+    std::map<int, int> later_rows;  // tuned per order, kept for the server's life
     int n_cs = 0;
     DevArray<int> d_ids;
+    hipGraphExec_t step_graph = nullptr;
 
     // counters (read under mu)
     uint64_t next_id = 1;
@@ -143,15 +161,21 @@ struct lb_server {
     void run();
     int admit(const Pending &p);
     int rebuild();
-    int run_chunk();
+    hipError_t enqueue_step(hipStream_t st);
+    hipError_t tune_order(int N);
+    int launch_chunk();
+    int wait_chunk();
     void drain();
-    void finish(uint64_t id, uint64_t tag, int status, double t_submit, double t_admit, std::vector<double> rows);
+    void fail_all(int rc);
+    void finish(uint64_t id, uint64_t tag, int status, double t_submit, double t_admit, std::vector<double> rows,
+                double nu_app);
 };
 
 void lb_server::finish(uint64_t id, uint64_t tag, int status, double t_submit, double t_admit,
-                       std::vector<double> rows)
+                       std::vector<double> rows, double nu_app)
 {
     lb_result r{};
+    r.nu_app = nu_app;
     r.id = id;
     r.tag = tag;
     r.status = status;
@@ -180,10 +204,14 @@ int lb_server::admit(const Pending &p)
     const lb_request &q = p.req;
     lb_sim *sim = lb_create(q.model | LB_FP32, q.Nx, q.Ny, q.tau, q.dt, q.ds, q.N);
     if (!sim) return lb_last_error();
-    int rc = lb_set_stream(sim, stream);
+    // set up on the admission stream (each call synchronises only that
+    // stream, not the chunk running on the compute stream), then step on the
+    // compute stream
+    int rc = lb_set_stream(sim, astream);
     if (rc == LB_OK) rc = lb_init(sim, q.rho, q.ux, q.uy);
     if (rc == LB_OK && q.ax) rc = lb_set_probe(sim, q.ax, q.ay, q.bx, q.by);
     if (rc == LB_OK) rc = lb_series_reserve(sim, q.nsteps / q.sample_every + 2);
+    if (rc == LB_OK) rc = lb_set_stream(sim, stream);
     if (rc != LB_OK) {
         lb_destroy(sim);
         return rc;
@@ -199,6 +227,9 @@ int lb_server::admit(const Pending &p)
     r.t_admit = now_s(t0);
     r.footprint = p.footprint;
     r.N = sim->cs ? 0 : sim->N;
+    r.dt = q.dt;
+    r.decay_k2 = q.decay_k2;
+    r.decay_omega = q.decay_omega;
     running.push_back(r);
     return LB_OK;
 }
@@ -239,7 +270,7 @@ int lb_server::rebuild()
             auto &v = fd[s->N];
             for (int t = 0; t < tiles; ++t) v.push_back({i, t});
             auto &v16 = fd16[s->N];
-            const int tiles16 = b.tiles_x * ((s->Ny + kFdLaterTileRows - 1) / kFdLaterTileRows);
+            const int tiles16 = b.tiles_x * ((s->Ny + 15) / 16);
             for (int t = 0; t < tiles16; ++t) v16.push_back({i, t});
         }
     }
@@ -269,31 +300,108 @@ int lb_server::rebuild()
     upload_lists(fd16, d_fd16, n_fd16);
     // the host vectors must outlive the copies
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    for (auto &kv : n_fd) {
+        if (e != hipSuccess) break;
+        if (!later_rows.count(kv.first)) e = tune_order(kv.first);
+    }
+    // capture one batched step of this running set
+    if (step_graph) {
+        (void)hipGraphExecDestroy(step_graph);
+        step_graph = nullptr;
+    }
+    if (e == hipSuccess && use_graphs) {
+        e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ec = enqueue_step(stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(stream, &g);
+            if (e == hipSuccess) e = ec;
+            if (e == hipSuccess) e = hipGraphInstantiate(&step_graph, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    }
     return dev_status(e);
 }
 
-int lb_server::run_chunk()
+// The launches of one batched step, in the order of the single-simulation
+// step (CS; per FD order the three Runge-Kutta stages), then the
+// diagnostics sums and the step counter.
+hipError_t lb_server::enqueue_step(hipStream_t st)
+{
+    hipError_t e = launch_cs_batch(d_slots.ptr, d_cs.ptr, n_cs, d_epoch, st);
+    for (auto &kv : n_fd) {
+        const int N = kv.first, rows = later_rows.count(N) ? later_rows[N] : 4;
+        const BatchWork *later = rows == 8 ? d_fd[N].ptr : d_fd16[N].ptr;
+        const int nlater = rows == 8 ? kv.second : n_fd16[N];
+        // stage 1 always on the canonical 64 x 32 tiles of the fused diagnostics
+        if (e == hipSuccess) e = launch_fd_batch(d_slots.ptr, d_fd[N].ptr, kv.second, N, 1, 8, d_epoch, st);
+        for (int stage = 2; stage <= 3 && e == hipSuccess; ++stage)
+            e = launch_fd_batch(d_slots.ptr, later, nlater, N, stage, rows, d_epoch, st);
+    }
+    if (e == hipSuccess) e = launch_finalize_batch(d_slots.ptr, d_ids.ptr, (int)running.size(), d_epoch, st);
+    if (e == hipSuccess) e = launch_epoch_advance(d_epoch, st);
+    return e;
+}
+
+// Later-stage tile height of FD order N: time the stage-2 launch over the
+// current work list with 64 x 16 and with 64 x 32 tiles and keep the faster
+// (the stage-2 output buffer is scratch between steps, so the timing leaves
+// every state unchanged; results do not depend on the choice).
+hipError_t lb_server::tune_order(int N)
+{
+    if (!tune_tiles) {
+        later_rows[N] = 4;
+        return hipSuccess;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    float best = 0.0f;
+    int pick = 4;
+    for (int rows : {4, 8}) {
+        const BatchWork *w = rows == 8 ? d_fd[N].ptr : d_fd16[N].ptr;
+        const int nw = rows == 8 ? n_fd[N] : n_fd16[N];
+        if (e == hipSuccess) e = launch_fd_batch(d_slots.ptr, w, nw, N, 2, rows, d_epoch, stream);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, stream);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_fd_batch(d_slots.ptr, w, nw, N, 2, rows, d_epoch, stream);
+        if (e == hipSuccess) e = hipEventRecord(b, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (rows == 4 || ms < best)) {
+            best = ms;
+            pick = rows;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e == hipSuccess) later_rows[N] = pick;
+    return e;
+}
+
+// Launch the next chunk of batched steps (asynchronously; chunk_done marks
+// its end).
+int lb_server::launch_chunk()
 {
     int g = chunk;
     for (const Running &r : running) g = std::min(g, r.nsteps - (epoch - r.start_epoch));
     g = std::max(g, 1);
     hipError_t e = hipSuccess;
-    for (int i = 0; i < g && e == hipSuccess; ++i) {
-        const int E = epoch + i;
-        e = launch_cs_batch(d_slots.ptr, d_cs.ptr, n_cs, E, stream);
-        for (auto &kv : n_fd) {
-            const int N = kv.first;
-            if (e == hipSuccess) e = launch_fd_batch(d_slots.ptr, d_fd[N].ptr, kv.second, N, 1, E, stream);
-            for (int stage = 2; stage <= 3 && e == hipSuccess; ++stage)
-                e = launch_fd_batch(d_slots.ptr, d_fd16[N].ptr, n_fd16[N], N, stage, E, stream);
-        }
-        if (e == hipSuccess) e = launch_finalize_batch(d_slots.ptr, d_ids.ptr, (int)running.size(), E, stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    for (int i = 0; i < g && e == hipSuccess; ++i) e = step_graph ? hipGraphLaunch(step_graph, stream) : enqueue_step(stream);
+    if (e == hipSuccess) e = hipEventRecord(chunk_done, stream);
+    if (e != hipSuccess) return dev_status(e);
     epoch += g;
+    in_flight = true;
     std::lock_guard<std::mutex> lk(mu);
     steps_launched += g;
-    return dev_status(e);
+    return LB_OK;
+}
+
+int lb_server::wait_chunk()
+{
+    if (!in_flight) return LB_OK;
+    in_flight = false;
+    return dev_status(hipEventSynchronize(chunk_done));
 }
 
 void lb_server::drain()
@@ -319,18 +427,44 @@ void lb_server::drain()
         int status = got >= 0 ? LB_OK : got;
         double fin[kDiag];
         if (status == LB_OK) status = lb_reduce(s, fin);
+        double nu = std::nan("");
         if (status == LB_OK) {
             rows.resize(6 * ((size_t)got + 1));
             rows[6 * got] = (double)r.nsteps;
             for (int j = 0; j < kDiag; ++j) rows[6 * got + 1 + j] = fin[j];
+            if (r.decay_k2 > 0.0) {
+                // apparent viscosity: decay rate of the amplitude A against
+                // t = step dt over every sample, over decay_k2
+                const int n = got + 1;
+                std::vector<double> t(n), amp(n);
+                for (int i = 0; i < n; ++i) {
+                    t[i] = rows[6 * i] * r.dt;
+                    amp[i] = rows[6 * i + 5];
+                }
+                double rate = 0.0;
+                if (fit_decay_rate(t.data(), amp.data(), n, r.decay_omega, &rate) == LB_OK) nu = rate / r.decay_k2;
+            }
         } else {
             rows.clear();
         }
         lb_destroy(s);
         used -= r.footprint;
-        finish(r.id, r.tag, status, r.t_submit, r.t_admit, std::move(rows));
+        finish(r.id, r.tag, status, r.t_submit, r.t_admit, std::move(rows), nu);
     }
     running.swap(keep);
+}
+
+void lb_server::fail_all(int rc)
+{
+    // a device error ends every running request
+    (void)hipStreamSynchronize(stream);
+    in_flight = false;
+    for (Running &r : running) {
+        lb_destroy(r.sim);
+        used -= r.footprint;
+        finish(r.id, r.tag, rc, r.t_submit, r.t_admit, {}, std::nan(""));
+    }
+    running.clear();
 }
 
 void lb_server::run()
@@ -347,46 +481,49 @@ void lb_server::run()
                 admit_now.push_back(queue.front());
                 queue.pop_front();
             }
-            if (running.empty() && admit_now.empty()) {
+            if (running.empty() && admit_now.empty() && !in_flight) {
                 used_snapshot = used;
                 running_snapshot = 0;
                 cv_work.wait_for(lk, std::chrono::milliseconds(5));
                 continue;
             }
         }
+        // 1. new simulations, set up while the chunk in flight runs
         for (const Pending &p : admit_now) {
             const int rc = admit(p);
             if (rc != LB_OK) {
                 used -= p.footprint;
-                finish(p.id, p.req.tag, rc, p.t_submit, now_s(t0), {});
+                finish(p.id, p.req.tag, rc, p.t_submit, now_s(t0), {}, std::nan(""));
             } else {
                 changed = true;
             }
         }
-        if (running.empty()) continue;
         const double tb = now_s(t0);
-        int rc = LB_OK;
-        if (changed) rc = rebuild();
-        changed = false;
-        if (rc == LB_OK) rc = run_chunk();
+        // 2. the chunk in flight, and the simulations it finished
+        int rc = wait_chunk();
         if (rc != LB_OK) {
-            // a device error ends every running request
-            for (Running &r : running) {
-                lb_destroy(r.sim);
-                used -= r.footprint;
-                finish(r.id, r.tag, rc, r.t_submit, r.t_admit, {});
-            }
-            running.clear();
+            fail_all(rc);
             continue;
         }
         const size_t before = running.size();
         drain();
         if (running.size() != before) changed = true;
+        // 3. descriptors and step graph of the new running set; 4. next chunk
+        if (!running.empty()) {
+            if (changed) rc = rebuild();
+            changed = false;
+            if (rc == LB_OK) rc = launch_chunk();
+            if (rc != LB_OK) {
+                fail_all(rc);
+                continue;
+            }
+        }
         std::lock_guard<std::mutex> lk(mu);
         busy_s += now_s(t0) - tb;
         used_snapshot = used;
         running_snapshot = (int)running.size();
     }
+    (void)wait_chunk();
 }
 
 extern "C" {
@@ -407,14 +544,32 @@ lb_server *lb_server_create(size_t hbm_budget_bytes, int max_slots, int chunk_st
     s->chunk = chunk_steps;
     s->t0 = std::chrono::steady_clock::now();
     if (hipGetDevice(&s->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->chunk_done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s->d_epoch, sizeof(int)) != hipSuccess ||
+        hipMemcpy(s->d_epoch, &s->epoch, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
+        if (s->d_epoch) (void)hipFree(s->d_epoch);
+        if (s->chunk_done) (void)hipEventDestroy(s->chunk_done);
+        if (s->astream) (void)hipStreamDestroy(s->astream);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         set_last_error(LB_EDEVICE);
         return nullptr;
     }
-    s->worker = std::thread([s] { s->run(); });
     return s;
+}
+
+int lb_server_configure(lb_server *s, int use_graphs, int tune_tiles)
+{
+    if (!s || (use_graphs != 0 && use_graphs != 1) || (tune_tiles != 0 && tune_tiles != 1))
+        return set_last_error(LB_EINVAL);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->started.load()) return set_last_error(LB_ESTATE);
+    s->use_graphs = use_graphs != 0;
+    s->tune_tiles = tune_tiles != 0;
+    return LB_OK;
 }
 
 int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
@@ -425,6 +580,9 @@ int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
     const bool probe_any = req->ax || req->ay || req->bx || req->by;
     const bool probe_all = req->ax && req->ay && req->bx && req->by;
     if (probe_any && !probe_all) return set_last_error(LB_EINVAL);
+    if (!(req->decay_k2 >= 0.0) || !std::isfinite(req->decay_k2) || !(req->decay_omega >= 0.0) ||
+        !std::isfinite(req->decay_omega) || (req->decay_k2 > 0.0 && !probe_all))
+        return set_last_error(LB_EINVAL);
     const int rc = validate_create(req->model | LB_FP32, req->Nx, req->Ny, req->tau, req->dt, req->ds, req->N);
     if (rc != LB_OK) return set_last_error(rc);
     ModelInfo mi{};
@@ -434,6 +592,7 @@ int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
     p.footprint = footprint_of(*req, mi);
     if (p.footprint > s->budget) return set_last_error(LB_EBUSY);
     std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->started.exchange(true)) s->worker = std::thread([s] { s->run(); });
     p.id = s->next_id++;
     p.t_submit = now_s(s->t0);
     s->queue.push_back(p);
@@ -496,7 +655,11 @@ void lb_server_destroy(lb_server *s)
     for (auto &kv : s->d_fd) kv.second.release();
     for (auto &kv : s->d_fd16) kv.second.release();
     s->d_ids.release();
+    if (s->step_graph) (void)hipGraphExecDestroy(s->step_graph);
+    if (s->d_epoch) (void)hipFree(s->d_epoch);
+    if (s->chunk_done) (void)hipEventDestroy(s->chunk_done);
     for (lb_result &r : s->done) std::free(r.samples);
+    if (s->astream) (void)hipStreamDestroy(s->astream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }

@@ -75,5 +75,7 @@ Params<CT> make_params(const lb_sim *s);
 int dev_status(hipError_t e);
 int diag_blocks_fused(const lb_sim *s);
 void finish_diag(const lb_sim *s, const double *raw, double vscale, double *out);
+// Decay rate of an amplitude series (lb_fit_decay): LB_OK or an LB_E* code.
+int fit_decay_rate(const double *t, const double *amp, int n, double omega, double *rate);
 
 }  // namespace lbm

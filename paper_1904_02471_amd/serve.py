@@ -20,13 +20,15 @@ class Request(ctypes.Structure):
                 ("tau", ctypes.c_double), ("dt", ctypes.c_double), ("ds", ctypes.c_double), ("N", ctypes.c_int),
                 ("rho", _dp), ("ux", _dp), ("uy", _dp),
                 ("ax", _dp), ("ay", _dp), ("bx", _dp), ("by", _dp),
-                ("nsteps", ctypes.c_int), ("sample_every", ctypes.c_int), ("tag", ctypes.c_uint64)]
+                ("nsteps", ctypes.c_int), ("sample_every", ctypes.c_int), ("tag", ctypes.c_uint64),
+                ("decay_k2", ctypes.c_double), ("decay_omega", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int),
                 ("nsamples", ctypes.c_int), ("samples", _dp),
-                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_finish", ctypes.c_double)]
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_finish", ctypes.c_double),
+                ("nu_app", ctypes.c_double)]
 
 
 _lib.lb_server_create.restype = ctypes.c_void_p
@@ -41,6 +43,10 @@ _lib.lb_server_clock.restype = ctypes.c_double
 _lib.lb_server_clock.argtypes = [ctypes.c_void_p]
 _lib.lb_server_stats.restype = ctypes.c_int
 _lib.lb_server_stats.argtypes = [ctypes.c_void_p, _dp]
+_lib.lb_server_configure.restype = ctypes.c_int
+_lib.lb_server_configure.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+_lib.lb_fit_decay.restype = ctypes.c_int
+_lib.lb_fit_decay.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp]
 _lib.lb_server_destroy.restype = None
 _lib.lb_server_destroy.argtypes = [ctypes.c_void_p]
 
@@ -53,14 +59,18 @@ class Server:
     """Python handle of an lb_server.  Keeps the host arrays of every
     submitted request alive until its result is polled."""
 
-    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=512, chunk_steps=32):
+    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=512, chunk_steps=32, use_graphs=True, tune_tiles=True):
         h = _lib.lb_server_create(int(hbm_budget_bytes), int(max_slots), int(chunk_steps))
         if not h:
             raise lb.LBError(lb.lb_last_error(), "lb_server_create")
         self._h = h
         self._keep = {}
+        rc = _lib.lb_server_configure(h, int(bool(use_graphs)), int(bool(tune_tiles)))
+        if rc != lb.LB_OK:
+            raise lb.LBError(rc, "lb_server_configure")
 
-    def submit(self, model, Nx, Ny, tau, dt, ds, N, rho, ux, uy, nsteps, sample_every, probe=None, tag=0):
+    def submit(self, model, Nx, Ny, tau, dt, ds, N, rho, ux, uy, nsteps, sample_every, probe=None, tag=0,
+               decay_k2=0.0, decay_omega=0.0):
         shp = (Ny, Nx)
         arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), shp)) for a in (rho, ux, uy)]
         pr = [None] * 4
@@ -68,7 +78,7 @@ class Server:
             pr = [np.ascontiguousarray(np.asarray(v, np.float64)) for v in probe]
         r = Request(int(model), int(Nx), int(Ny), float(tau), float(dt), float(ds), int(N),
                     _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]), _ptr(pr[0]), _ptr(pr[1]), _ptr(pr[2]), _ptr(pr[3]),
-                    int(nsteps), int(sample_every), int(tag))
+                    int(nsteps), int(sample_every), int(tag), float(decay_k2), float(decay_omega))
         rid = ctypes.c_uint64(0)
         rc = _lib.lb_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid))
         if rc != lb.LB_OK:
@@ -87,7 +97,8 @@ class Server:
             r = buf[i]
             samples = np.ctypeslib.as_array(r.samples, shape=(r.nsamples, 6)).copy() if r.nsamples else np.zeros((0, 6))
             out.append({"id": r.id, "tag": r.tag, "status": r.status, "samples": samples,
-                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_finish": r.t_finish})
+                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_finish": r.t_finish,
+                        "nu_app": r.nu_app})
             _lib.lb_server_release(self._h, ctypes.byref(r))
             self._keep.pop(r.id, None)
         return out
@@ -111,6 +122,18 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def fit_decay(t, amp, omega=0.0):
+    """lb_fit_decay: decay rate of the amplitude series amp(t) (FP64 least
+    squares of ln|amp| on {1, -t}, with omega > 0 also cos/sin(omega t))."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    a = np.ascontiguousarray(amp, dtype=np.float64)
+    out = np.zeros(1)
+    rc = _lib.lb_fit_decay(_ptr(t), _ptr(a), int(t.size), float(omega), _ptr(out))
+    if rc != lb.LB_OK:
+        raise lb.LBError(rc, "lb_fit_decay")
+    return float(out[0])
 
 
 def wait_all(server, n, timeout_s=600.0):

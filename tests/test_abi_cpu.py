@@ -134,3 +134,24 @@ def test_imex_lifts_the_stiffness_bound():
         lb._lib.lb_destroy(h)
     else:
         assert lb.lb_last_error() not in (lb.LB_ESTIFF, lb.LB_EINVAL, lb.LB_ECFL)
+
+
+@pytest.mark.parametrize("omega", [0.0, 3.7])
+def test_fit_decay_against_oracle_fit(omega):
+    """lb_fit_decay (host FP64 least squares) against the oracle package's
+    fit of the same series (numpy lstsq), on a decaying, modulated series."""
+    from oracle import exact
+    from paper_1904_02471_amd import serve
+    t = np.linspace(0.0, 8.0, 401)
+    amp = 0.01 * np.exp(-0.37 * t + 1e-3 * np.cos(3.7 * t + 0.4))  # ln|amp| exactly in the fitted form
+    got = serve.fit_decay(t, amp, omega)
+    want = exact.fit_decay_rate(t, amp) if omega == 0 else exact.fit_decay_rate_acoustic(t, amp, omega)
+    assert got == pytest.approx(want, rel=1e-12, abs=1e-15)
+    if omega:
+        assert got == pytest.approx(0.37, rel=1e-12)
+    else:
+        assert got == pytest.approx(0.37, rel=1e-3)   # the modulation biases the plain fit
+    with pytest.raises(lb.LBError):
+        serve.fit_decay(t[:2], amp[:2])
+    with pytest.raises(lb.LBError):
+        serve.fit_decay(t, np.where(t > 4, 0.0, amp))

@@ -1,10 +1,14 @@
 """The serving form: many simulations in one batched launch, admitted by
 memory footprint while others run.  Each result must be the same alone and
 in the mix, and the same as a single-simulation run of the same request."""
+import math
+import time
+
 import numpy as np
 import pytest
 
 import oracle
+from oracle import exact
 from paper_1904_02471_amd import lb, serve, workloads
 
 pytestmark = pytest.mark.gpu
@@ -109,3 +113,85 @@ def test_admission_by_memory_budget():
         srv.submit(sample_every=EVERY, **kw)
     assert err.value.code == lb.LB_EINVAL
     srv.close()
+
+
+def run_server_cfg(entries, use_graphs, tune_tiles=True, chunk=16):
+    srv = serve.Server(8 << 30, 64, chunk, use_graphs=use_graphs, tune_tiles=tune_tiles)
+    fields = serve.field_cache()
+    for i, e in enumerate(entries):
+        srv.submit(sample_every=EVERY, tag=i, **serve.trace_request(e, fields))
+    res = serve.wait_all(srv, len(entries), 120)
+    srv.close()
+    by_tag = {r["tag"]: r for r in res}
+    return [by_tag[i] for i in range(len(entries))]
+
+
+def test_graph_replay_equals_plain_launches():
+    """The captured batched step replays exactly the kernels launched one by
+    one: bitwise the same series, whatever later-stage tile height the
+    tuner picked."""
+    print("case: serving graphs vs plain launches", flush=True)
+    mix = small_mix()
+    g = run_server_cfg(mix, True)
+    p = run_server_cfg(mix, False, tune_tiles=False)
+    for e, a, b in zip(mix, g, p):
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.array_equal(a["samples"], b["samples"]), e
+
+
+def test_admission_while_running():
+    """Requests submitted after the first batched chunk has started join the
+    running batch (admitted before the earlier requests finish) and give the
+    single-simulation results bit for bit."""
+    print("case: serving mid-run admission", flush=True)
+    first = [{"kind": "tgv", "side": 256, "model": "cs", "tau_std": 0.6, "steps": 400},
+             {"kind": "tgv", "side": 128, "model": "fd16", "tau_std": 0.8, "steps": 120}]
+    late = [{"kind": "shear", "side": 96, "model": "fd16", "tau_std": 0.7, "steps": 37},
+            {"kind": "tgv", "side": 160, "model": "cs", "tau_std": 0.9, "steps": 51}]
+    srv = serve.Server(8 << 30, 64, 8)
+    fields = serve.field_cache()
+    for i, e in enumerate(first):
+        srv.submit(sample_every=EVERY, tag=i, **serve.trace_request(e, fields))
+    t_end = time.time() + 60
+    while srv.stats()["batch_steps"] < 1:
+        assert time.time() < t_end, "no batched step launched"
+        time.sleep(1e-3)
+    for i, e in enumerate(late):
+        srv.submit(sample_every=EVERY, tag=len(first) + i, **serve.trace_request(e, fields))
+    res = {r["tag"]: r for r in serve.wait_all(srv, len(first) + len(late), 120)}
+    srv.close()
+    entries = first + late
+    for i, e in enumerate(entries):
+        assert res[i]["status"] == 0
+        assert np.array_equal(res[i]["samples"], single_run(e)), e
+    # the late requests ran beside the first ones
+    assert min(res[i]["t_admit"] for i in (2, 3)) < res[0]["t_finish"]
+
+
+def test_apparent_viscosity_of_results():
+    """nu_app of a served result: the library's FP64 fit of its amplitude
+    series against the oracle package's fit of the same series."""
+    print("case: serving nu_app", flush=True)
+    ents = [{"kind": "tgv", "side": 64, "model": "cs", "tau_std": 0.7, "steps": 300},
+            {"kind": "shear", "side": 64, "model": "fd16", "tau_std": 0.8, "steps": 200}]
+    srv = serve.Server(8 << 30, 64, 16)
+    fields = serve.field_cache()
+    ks = []
+    for i, e in enumerate(ents):
+        kw = serve.trace_request(e, fields)
+        k = 2 * math.pi / e["side"] if e["model"] == "cs" else 2 * math.pi
+        k2 = 2 * k * k if e["kind"] == "tgv" else k * k
+        ks.append(k)
+        srv.submit(sample_every=EVERY, tag=i, decay_k2=k2, **kw)
+    res = {r["tag"]: r for r in serve.wait_all(srv, len(ents), 120)}
+    srv.close()
+    for i, e in enumerate(ents):
+        kw = serve.trace_request(e, fields)
+        s = res[i]["samples"]
+        want = exact.apparent_viscosity(s[:, 0] * kw["dt"], s[:, 5], ks[i], e["kind"])
+        nu = res[i]["nu_app"]
+        print("%s %s nu_app %.9e oracle fit %.9e" % (e["model"], e["kind"], nu, want), flush=True)
+        assert nu == pytest.approx(want, rel=1e-10)
+        # and close to the viscosity the request was set up with
+        nu0 = (e["tau_std"] - 0.5) / 3.0 if e["model"] == "cs" else kw["tau"]
+        assert nu == pytest.approx(nu0, rel=0.05)
