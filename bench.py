@@ -91,12 +91,15 @@ def make_sims(lb, workloads, units, n, stream):
 
 def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
     """CS D2Q9 plain steps on the n x n Taylor-Green vortex (tau = 0.55) with
-    FP32 and FP16-shifted storage: at 4096^2 the two state buffers (1.2 GB /
-    0.6 GB) exceed the 256 MB last-level cache, so the byte rate is the HBM
-    rate.  Autotuned launch shapes; plain steps as the library runs them."""
+    FP32, FP16-shifted and FP16 reference-shifted storage: at 4096^2 the two
+    state buffers (1.2 GB / 0.6 GB) exceed the 256 MB last-level cache, so the
+    byte rate is the HBM rate.  Bytes per node-step: 2 x 9 stored values, plus
+    the 4-byte reference velocity of the reference-shifted form.  Autotuned
+    launch shapes; plain steps as the library runs them."""
     import torch
     out = {"grid": [n, n], "steps": steps}
-    for name, prec, s in (("fp32", lb.LB_FP32, 4), ("fp16_shifted", lb.LB_FP16_SHIFTED, 2)):
+    for name, prec, s in (("fp32", lb.LB_FP32, 4), ("fp16_shifted", lb.LB_FP16_SHIFTED, 2),
+                          ("fp16_ref", lb.LB_FP16_REF, 2)):
         sim = lb.Sim(lb.LB_CS_D2Q9, n, n, 0.55, 1.0, 1.0, 2, precision=prec)
         sim.set_stream(stream.cuda_stream)
         r, ux, uy, _ = workloads.taylor_green(n, n, 0.01, 1.0 / 3.0)
@@ -112,7 +115,7 @@ def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
             b.record(stream)
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
-        bpn = 18 * s
+        bpn = 18 * s + (4 if prec == lb.LB_FP16_REF else 0)
         gbs = bpn * n * n / (ms * 1e-3) / 1e9
         out[name] = {"ms_per_step": round(ms, 5), "mlups": round(n * n / (ms * 1e-3) / 1e6, 1),
                      "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),

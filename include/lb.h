@@ -57,7 +57,18 @@ enum lb_model {
 enum lb_precision {
     LB_FP32 = 0,
     LB_FP16_SHIFTED = 1 << 8,
-    LB_FP64 = 2 << 8
+    LB_FP64 = 2 << 8,
+    /* collision-streaming only, periodic: FP16 storage of the departure from a
+     * reference equilibrium, 2^12 (g_k - R_k(U(x))) (the factor keeps small
+     * departures in the FP16 normal range) with R_k(U) the second-order
+     * equilibrium at (rho0, rho0 U) less w_k rho0 (Section 2) and U a
+     * per-node reference velocity stored as two FP16 values (4 more bytes
+     * per node: 40 bytes per node-step instead of 36).  lb_init takes U from
+     * the initial velocity, lb_set_state from the state's.  For a flow near
+     * its reference (a decaying wave or vortex) the stored departures are
+     * orders of magnitude below g_k, and so is the noise of their
+     * stochastic rounding; arithmetic stays FP32. */
+    LB_FP16_REF = 3 << 8
 };
 #define LB_PRECISION_MASK (3 << 8)
 

@@ -34,7 +34,7 @@ int fail(int code)
 
 namespace lbm {
 
-size_t elem_size(Prec p) { return p == P16 ? 2 : (p == P64 ? 8 : 4); }
+size_t elem_size(Prec p) { return (p == P16 || p == P16R) ? 2 : (p == P64 ? 8 : 4); }
 
 // CS D2Q9 constants in the arithmetic type, chosen so that the sums that
 // carry mass and momentum are exact as real numbers: w1 = fl(1/9), w5 = 1/36
@@ -125,6 +125,14 @@ Params<CT> make_params(const lb_sim *s)
         cs_exact_constants(p);
     else
         fd_moment_defects(p);
+    if (s->prec == P16R) {
+        // the FP32 constants of the reference shift, whatever CT is
+        Params<float> pf{};
+        cs_exact_constants(pf);
+        p.ref = s->d_ref;
+        const float c[8] = {pf.cs_w0, pf.cs_w1, pf.cs_w5, pf.cs_a1, pf.cs_a5, 0.5f, 0.125f, (float)s->rho0};
+        for (int i = 0; i < 8; ++i) p.ref_c[i] = c[i];
+    }
     return p;
 }
 
@@ -134,6 +142,8 @@ void free_buffers(lb_sim *s)
         if (s->buf[i]) (void)hipFree(s->buf[i]);
         s->buf[i] = nullptr;
     }
+    if (s->d_ref) (void)hipFree(s->d_ref);
+    s->d_ref = nullptr;
 }
 
 int alloc_buffers(lb_sim *s)
@@ -154,6 +164,15 @@ int alloc_buffers(lb_sim *s)
         }
         if (hipMemsetAsync(s->buf[i], 0, s->buf_bytes, s->stream) != hipSuccess) return LB_EDEVICE;
     }
+    if (s->prec == P16R) {
+        const size_t bytes = (size_t)s->pitch * s->Ny * sizeof(uint32_t);
+        if (hipMalloc(&s->d_ref, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            free_buffers(s);
+            return LB_ENOMEM;
+        }
+        if (hipMemsetAsync(s->d_ref, 0, bytes, s->stream) != hipSuccess) return LB_EDEVICE;
+    }
     return LB_OK;
 }
 
@@ -168,7 +187,8 @@ template <typename F>
 hipError_t with_type(lb_sim *s, F &&f)
 {
     switch (s->prec) {
-    case P16: return f((__half *)nullptr);
+    case P16:
+    case P16R: return f((__half *)nullptr);
     case P64: return f((double *)nullptr);
     default: return f((float *)nullptr);
     }
@@ -235,7 +255,7 @@ hipError_t step_once(lb_sim *s, bool with_diag)
 // every step, which a replayed graph would repeat.
 int graph_len(const lb_sim *s)
 {
-    if (s->prec == P16) return 0;
+    if (s->prec == P16 || s->prec == P16R) return 0;
     int g = s->graph_steps < 0 ? (s->cs ? 8 : 4) : s->graph_steps;
     if (s->cs && (g & 1)) ++g;
     return g;
@@ -364,7 +384,9 @@ int validate_create(int model_flags, int Nx, int Ny, double tau, double dt, doub
 {
     const int model = model_flags & 0xff;
     const int precbits = model_flags & LB_PRECISION_MASK;
-    if ((model_flags & ~(0xff | LB_PRECISION_MASK | LB_IMEX)) != 0 || precbits == (3 << 8)) return LB_EINVAL;
+    if ((model_flags & ~(0xff | LB_PRECISION_MASK | LB_IMEX)) != 0) return LB_EINVAL;
+    // storage relative to a reference equilibrium: collision-streaming only
+    if (precbits == LB_FP16_REF && model != LB_CS_D2Q9) return LB_EINVAL;
     const bool imex = (model_flags & LB_IMEX) != 0;
     ModelInfo mi{};
     if (!(tau > 0) || !(dt > 0) || !(ds > 0) || !std::isfinite(tau) || !std::isfinite(dt) || !std::isfinite(ds) ||
@@ -460,7 +482,7 @@ lb_sim *lb_create(int model_flags, int Nx, int Ny, double tau, double dt, double
     }
     s->model = model;
     s->imex = (model_flags & LB_IMEX) != 0;
-    s->prec = precbits == LB_FP16_SHIFTED ? P16 : (precbits == LB_FP64 ? P64 : P32);
+    s->prec = precbits == LB_FP16_SHIFTED ? P16 : (precbits == LB_FP64 ? P64 : (precbits == LB_FP16_REF ? P16R : P32));
     s->cs = cs;
     s->Nx = Nx;
     s->Ny = Ny;
@@ -523,6 +545,7 @@ int lb_set_bc_x(lb_sim *s, double rho_left, double rho_right)
     if (!s || !(rho_left > 0) || !(rho_right > 0) || !std::isfinite(rho_left) || !std::isfinite(rho_right))
         return fail(LB_EINVAL);
     if (s->ready) return fail(LB_ESTATE);
+    if (s->prec == P16R) return fail(LB_EINVAL);  // periodic only
     drop_graphs(s);
     const bool relayout = s->cs && !s->fixed;
     s->fixed = true;
@@ -570,7 +593,8 @@ size_t lb_device_bytes(const lb_sim *s)
     if (!s) return 0;
     return s->nbuf * s->buf_bytes + sizeof(double) * ((kDiag + 1) * (size_t)s->partial_blocks + kDiag) +
            (s->d_probe64 ? 2 * (s->Nx + s->Ny) * (sizeof(double) + sizeof(float)) : 0) +
-           sizeof(double) * kDiag * (size_t)s->series_cap;
+           sizeof(double) * kDiag * (size_t)s->series_cap +
+           (s->d_ref ? (size_t)s->pitch * s->Ny * sizeof(uint32_t) : 0);
 }
 
 // Upload fields / state through a temporary device buffer.
@@ -625,7 +649,9 @@ int lb_init(lb_sim *s, const double *rho, const double *ux, const double *uy)
         const Params<double> p = make_params<double>(s);
         hipError_t e = with_type(s, [&](auto *tag) {
             using T = std::remove_pointer_t<decltype(tag)>;
-            hipError_t e = launch_init<T>(bufp<T>(s, 0), d, d + n, d + 2 * n, s->cs, p, s->stream);
+            hipError_t e = hipSuccess;
+            if (s->d_ref) e = launch_ref_from_velocity(s->d_ref, d + n, d + 2 * n, p, 1.0 / s->mi.cl, s->stream);
+            if (e == hipSuccess) e = launch_init<T>(bufp<T>(s, 0), d, d + n, d + 2 * n, s->cs, p, s->stream);
             if (e == hipSuccess && !s->cs)
                 e = launch_fd_moments<T>(bufp<T>(s, 0), make_params<typename Arith<T>::type>(s), s->stream);
             return e;
@@ -661,7 +687,9 @@ int lb_set_state(lb_sim *s, const double *f)
         const Params<double> p = make_params<double>(s);
         hipError_t e = with_type(s, [&](auto *tag) {
             using T = std::remove_pointer_t<decltype(tag)>;
-            hipError_t e = launch_set_state<T>(bufp<T>(s, 0), d, s->cs, p, s->stream);
+            hipError_t e = hipSuccess;
+            if (s->d_ref) e = launch_ref_from_state(s->d_ref, d, p, s->stream);
+            if (e == hipSuccess) e = launch_set_state<T>(bufp<T>(s, 0), d, s->cs, p, s->stream);
             if (e == hipSuccess && !s->cs)
                 e = launch_fd_moments<T>(bufp<T>(s, 0), make_params<typename Arith<T>::type>(s), s->stream);
             return e;

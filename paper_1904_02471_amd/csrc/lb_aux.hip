@@ -66,6 +66,86 @@ __device__ __forceinline__ long long store_index(const Params<double> &p, bool c
 template <typename T>
 __device__ __forceinline__ double ldd(const T *ptr) { return (double)ld(ptr); }
 
+// Storage node of the canonical value f_k(x, y) (store_index's position).
+__device__ __forceinline__ void store_node(const Params<double> &p, bool cs, int k, int x, int y, int &xs, int &ys)
+{
+    xs = x;
+    ys = y;
+    if (cs) {
+        xs = x - (p.ki[k] - 1);
+        ys = wrapi(y - (p.kj[k] - 1), p.Ny);
+        if (!p.fixed_x) xs = wrapi(xs, p.Nx);
+    }
+}
+
+// Reference shift of population k stored at node (xs, ys): 0 unless the
+// storage is relative to a reference equilibrium (LB_FP16_REF, CS).
+__device__ __forceinline__ double ref_shift(const Params<double> &p, int k, int xs, int ys)
+{
+    if (!p.ref) return 0.0;
+    float ux, uy;
+    ref_unpack(p.ref[(long long)ys * p.pitch + xs], ux, uy);
+    return (double)cs_ref_pop(k, ux, uy, p.ref_c);
+}
+
+// Shifted value g_k = f_k - w_k rho0 of the canonical state at (x, y) (under
+// LB_FP16_REF the stored value is the scaled departure from the reference).
+template <typename T>
+__device__ __forceinline__ double stored_g(const T *src, const Params<double> &p, bool cs, int k, int x, int y)
+{
+    int xs, ys;
+    store_node(p, cs, k, x, y, xs, ys);
+    const double v = ldd(src + store_index(p, cs, k, x, y));
+    if (!p.ref) return v;
+    return v * (double)kRefInvScale + ref_shift(p, k, xs, ys);
+}
+
+// Store the shifted value g of f_k(x, y) (less the reference shift, if any).
+template <typename T>
+__device__ __forceinline__ void store_g(T *dst, const Params<double> &p, bool cs, int k, int x, int y, double g)
+{
+    int xs, ys;
+    store_node(p, cs, k, x, y, xs, ys);
+    if (!p.ref)
+        store_from(dst + store_index(p, cs, k, x, y), g);
+    else
+        store_from(dst + store_index(p, cs, k, x, y), (g - ref_shift(p, k, xs, ys)) * (double)kRefScale);
+}
+
+// Reference velocity of LB_FP16_REF: (ux, uy) / c_l per node, rounded to
+// FP16 (the collision works in lattice velocity units).
+__global__ __launch_bounds__(kAuxThreads) void ref_from_velocity_kernel(uint32_t *ref, const double *ux,
+                                                                        const double *uy, const Params<double> p,
+                                                                        double inv_cl)
+{
+    const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
+    if (n >= (long long)p.Nx * p.Ny) return;
+    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    const unsigned short hx = __builtin_bit_cast(unsigned short, (_Float16)(ux[n] * inv_cl));
+    const unsigned short hy = __builtin_bit_cast(unsigned short, (_Float16)(uy[n] * inv_cl));
+    ref[(long long)y * p.pitch + x] = (uint32_t)hx | ((uint32_t)hy << 16);
+}
+
+// The same from the velocity of a canonical state f [K][Ny][Nx] (FP64).
+__global__ __launch_bounds__(kAuxThreads) void ref_from_state_kernel(uint32_t *ref, const double *f,
+                                                                     const Params<double> p)
+{
+    const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
+    const long long nodes = (long long)p.Nx * p.Ny;
+    if (n >= nodes) return;
+    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    double r = 0.0, jx = 0.0, jy = 0.0;
+    for (int k = 0; k < p.K; ++k) {
+        const double fk = f[k * nodes + n];
+        r += fk;
+        jx += fk * (double)(p.ki[k] - 1);  // lattice units: e_k
+        jy += fk * (double)(p.kj[k] - 1);
+    }
+    const unsigned short hx = __builtin_bit_cast(unsigned short, (_Float16)(jx / r));
+    const unsigned short hy = __builtin_bit_cast(unsigned short, (_Float16)(jy / r));
+    ref[(long long)y * p.pitch + x] = (uint32_t)hx | ((uint32_t)hy << 16);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kAuxThreads) void init_kernel(T *dst, const double *rho, const double *ux,
                                                            const double *uy, bool cs, const Params<double> p)
@@ -75,7 +155,7 @@ __global__ __launch_bounds__(kAuxThreads) void init_kernel(T *dst, const double 
     const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
     const double r = rho[n];
     const double ax = ux[n] / p.cs, ay = uy[n] / p.cs;
-    for (int k = 0; k < p.K; ++k) store_from(dst + store_index(p, cs, k, x, y), feq_shifted(p, k, r - p.rho0, r, ax, ay));
+    for (int k = 0; k < p.K; ++k) store_g(dst, p, cs, k, x, y, feq_shifted(p, k, r - p.rho0, r, ax, ay));
 }
 
 template <typename T>
@@ -97,7 +177,7 @@ __global__ __launch_bounds__(kAuxThreads) void get_state_kernel(const T *src, do
     const long long nodes = (long long)p.Nx * p.Ny;
     if (n >= nodes) return;
     const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
-    for (int k = 0; k < p.K; ++k) f[k * nodes + n] = ldd(src + store_index(p, cs, k, x, y)) + p.w[k] * p.rho0;
+    for (int k = 0; k < p.K; ++k) f[k * nodes + n] = stored_g(src, p, cs, k, x, y) + p.w[k] * p.rho0;
 }
 
 template <typename T>
@@ -108,7 +188,7 @@ __global__ __launch_bounds__(kAuxThreads) void set_state_kernel(T *dst, const do
     const long long nodes = (long long)p.Nx * p.Ny;
     if (n >= nodes) return;
     const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
-    for (int k = 0; k < p.K; ++k) store_from(dst + store_index(p, cs, k, x, y), f[k * nodes + n] - p.w[k] * p.rho0);
+    for (int k = 0; k < p.K; ++k) store_g(dst, p, cs, k, x, y, f[k * nodes + n] - p.w[k] * p.rho0);
 }
 
 // moments of node n: drho = sum g_k, j = sum g_k v_k (sum w_k v_k = 0)
@@ -118,7 +198,7 @@ __device__ __forceinline__ void node_moments(const T *src, bool cs, const Params
 {
     drho = jx = jy = 0.0;
     for (int k = 0; k < p.K; ++k) {
-        const double g = ldd(src + store_index(p, cs, k, x, y));
+        const double g = stored_g(src, p, cs, k, x, y);
         drho += g;
         jx += g * p.vx[k];
         jy += g * p.vy[k];
@@ -252,6 +332,21 @@ hipError_t launch_init(T *dst, const double *rho, const double *ux, const double
 {
     hipLaunchKernelGGL(init_kernel<T>, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s, dst, rho,
                        ux, uy, cs, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_from_velocity(uint32_t *ref, const double *ux, const double *uy, const Params<double> &p,
+                                    double inv_cl, hipStream_t s)
+{
+    hipLaunchKernelGGL(ref_from_velocity_kernel, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s,
+                       ref, ux, uy, p, inv_cl);
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_from_state(uint32_t *ref, const double *f, const Params<double> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(ref_from_state_kernel, dim3(grid_for((long long)p.Nx * p.Ny)), dim3(kAuxThreads), 0, s, ref,
+                       f, p);
     return hipGetLastError();
 }
 

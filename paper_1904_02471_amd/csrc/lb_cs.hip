@@ -6,23 +6,23 @@ namespace lbm {
 
 namespace {
 
-template <typename T, bool FIXED, bool DIAG>
+template <typename T, bool FIXED, bool DIAG, bool REF>
 __global__ __launch_bounds__(kCsThreads) void cs_step_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                              const Params<typename Arith<T>::type> p,
                                                              const DiagArgs<typename Arith<T>::type> d)
 {
-    cs_row<T, FIXED, DIAG>(src, dst, p, d, blockIdx.x, blockIdx.x);
+    cs_row<T, FIXED, DIAG, REF>(src, dst, p, d, blockIdx.x, blockIdx.x);
 }
 
-template <typename T, bool DIAG>
+template <typename T, bool DIAG, bool REF>
 __global__ __launch_bounds__(1024) void cs_step_vec_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                                  const Params<typename Arith<T>::type> p,
                                                                  const DiagArgs<typename Arith<T>::type> d)
 {
-    cs_row_vec<T, DIAG>(src, dst, p, d, blockIdx.x, blockIdx.x);
+    cs_row_vec<T, DIAG, REF>(src, dst, p, d, blockIdx.x, blockIdx.x);
 }
 
-template <typename T, bool FIXED>
+template <typename T, bool FIXED, bool REF>
 hipError_t launch_cs_t(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
                        const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int threads)
 {
@@ -31,18 +31,18 @@ hipError_t launch_cs_t(const T *src, T *dst, const Params<typename Arith<T>::typ
         // sampled steps keep the canonical size (their diagnostics sum per thread)
         const dim3 vblock(diag || threads <= 0 ? cs_vec_threads<T>(p.Nx) : threads);
         if (diag) {
-            hipLaunchKernelGGL((cs_step_vec_kernel<T, true>), grid, vblock, 0, s, src, dst, p, *diag);
+            hipLaunchKernelGGL((cs_step_vec_kernel<T, true, REF>), grid, vblock, 0, s, src, dst, p, *diag);
         } else {
             DiagArgs<typename Arith<T>::type> none{};
-            hipLaunchKernelGGL((cs_step_vec_kernel<T, false>), grid, vblock, 0, s, src, dst, p, none);
+            hipLaunchKernelGGL((cs_step_vec_kernel<T, false, REF>), grid, vblock, 0, s, src, dst, p, none);
         }
         return hipGetLastError();
     }
     if (diag) {
-        hipLaunchKernelGGL((cs_step_kernel<T, FIXED, true>), grid, block, 0, s, src, dst, p, *diag);
+        hipLaunchKernelGGL((cs_step_kernel<T, FIXED, true, REF>), grid, block, 0, s, src, dst, p, *diag);
     } else {
         DiagArgs<typename Arith<T>::type> none{};
-        hipLaunchKernelGGL((cs_step_kernel<T, FIXED, false>), grid, block, 0, s, src, dst, p, none);
+        hipLaunchKernelGGL((cs_step_kernel<T, FIXED, false, REF>), grid, block, 0, s, src, dst, p, none);
     }
     return hipGetLastError();
 }
@@ -55,8 +55,12 @@ template <typename T>
 hipError_t launch_cs_step(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
                           const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int threads)
 {
-    if (p.fixed_x) return launch_cs_t<T, true>(src, dst, p, diag, s, threads);
-    return launch_cs_t<T, false>(src, dst, p, diag, s, threads);
+    if constexpr (std::is_same<T, __half>::value) {
+        // FP16 relative to a reference equilibrium (periodic only)
+        if (p.ref) return p.fixed_x ? hipErrorInvalidValue : launch_cs_t<T, false, true>(src, dst, p, diag, s, threads);
+    }
+    if (p.fixed_x) return launch_cs_t<T, true, false>(src, dst, p, diag, s, threads);
+    return launch_cs_t<T, false, false>(src, dst, p, diag, s, threads);
 }
 
 template hipError_t launch_cs_step<float>(const float *, float *, const Params<float> &, const DiagArgs<float> *,

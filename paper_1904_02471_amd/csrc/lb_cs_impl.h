@@ -213,11 +213,16 @@ struct Chunk {
 
 // One row y of the step (all threads of a 256-thread workgroup); with DIAG
 // the diagnostics of the row's input state go to partial[diag_block].
-template <typename T, bool FIXED, bool DIAG>
+// REF (FP16 storage only, periodic): the stored values are the departures
+// from the reference equilibrium of their node (cs_ref_pop), scaled by
+// kRefScale; a pulled value is unscaled and gets the shift of its source
+// node added, a stored one the shift of its own node removed and is scaled.
+template <typename T, bool FIXED, bool DIAG, bool REF = false>
 __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict__ dst,
                                        const Params<typename Arith<T>::type> &p,
                                        const DiagArgs<typename Arith<T>::type> &d, int y, int diag_block)
 {
+    static_assert(!REF || (std::is_same<T, __half>::value && !FIXED), "reference shift: FP16, periodic");
     using CT = typename Arith<T>::type;
     const int Nx = p.Nx;
     const int ym = (y == 0) ? p.Ny - 1 : y - 1;
@@ -256,7 +261,24 @@ __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict_
         g[6] = ld(rs + 6 * P + xp);  // NW from (x+1, y-1)
         g[7] = ld(rn + 7 * P + xp);  // SW from (x+1, y+1)
         g[8] = ld(rn + 8 * P + xm);  // SE from (x-1, y+1)
+        if constexpr (REF) {
+            const uint32_t *u0 = p.ref + (long long)y * p.pitch, *us = p.ref + (long long)ym * p.pitch,
+                           *un = p.ref + (long long)yp * p.pitch;
+            const uint32_t src_u[9] = {u0[x], u0[xm], us[x], u0[xp], un[x], us[xm], us[xp], un[xp], un[xm]};
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                float ux, uy;
+                ref_unpack(src_u[k], ux, uy);
+                g[k] = __builtin_fmaf(g[k], kRefInvScale, cs_ref_pop(k, ux, uy, p.ref_c));
+            }
+        }
         const CsMoments<CT> m = cs_collide(g, out9, c);
+        if constexpr (REF) {
+            float ux, uy;
+            ref_unpack(p.ref[(long long)y * p.pitch + x], ux, uy);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) out9[k] = (out9[k] - cs_ref_pop(k, ux, uy, p.ref_c)) * kRefScale;
+        }
         CsRand<T> rnd(y * Nx + x, p.salt);
 #pragma unroll
         for (int k = 0; k < 9; ++k) store_state(orow + k * P + x, out9[k], rnd.next());
@@ -290,13 +312,14 @@ __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict_
 // same values as cs_row, with full-width memory accesses.  Any workgroup
 // size that is a multiple of 64 (up to 1024) works; with one chunk per
 // thread all loads of a row are in flight at once.
-template <typename T, bool DIAG>
+template <typename T, bool DIAG, bool REF = false>
 __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restrict__ dst,
                                            const Params<typename Arith<T>::type> &p,
                                            const DiagArgs<typename Arith<T>::type> &d, int y, int diag_block)
 {
     using CT = typename Arith<T>::type;
     constexpr int W = Chunk<T>::W;
+    static_assert(!REF || std::is_same<T, __half>::value, "reference shift: FP16 storage");
     static_assert(!std::is_same<T, __half>::value || W % 2 == 0, "FP16 chunks convert node pairs");
     const int Nx = p.Nx, nch = Nx / W;
     const int ym = (y == 0) ? p.Ny - 1 : y - 1;
@@ -355,6 +378,28 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
             r6 = rs[6 * P + xp];
             r7 = rn[7 * P + xp];
         }
+        // REF: reference velocities of x-1 .. x+W in rows y (c), y-1 (s), y+1 (n)
+        uint32_t rc[W + 2], rs_[W + 2], rn_[W + 2];
+        if constexpr (REF) {
+            const uint32_t *u0 = p.ref + (long long)y * p.pitch, *us = p.ref + (long long)ym * p.pitch,
+                           *un = p.ref + (long long)yp * p.pitch;
+            const int xm = (x == 0) ? Nx - 1 : x - 1, xp = (x + W == Nx) ? 0 : x + W;
+            auto row = [&](const uint32_t *u, uint32_t *o) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(u + x);  // W = 4 nodes, 16 bytes
+                o[1] = q.x;
+                o[2] = q.y;
+                o[3] = q.z;
+                o[4] = q.w;
+                uint32_t l = (uint32_t)__shfl_up((int)q.w, 1, 64), r = (uint32_t)__shfl_down((int)q.x, 1, 64);
+                if (lane == 0) l = u[xm];
+                if (lane == 63 || v == nch - 1) r = u[xp];
+                o[0] = l;
+                o[W + 1] = r;
+            };
+            row(u0, rc);
+            row(us, rs_);
+            row(un, rn_);
+        }
         Chunk<T> out[9];
         float held[9];  // FP16: the even node's values awaiting their pair
 #pragma unroll
@@ -369,7 +414,24 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
             g[6] = to_ct<T>(j < W - 1 ? in[6].get(j + 1) : r6);
             g[7] = to_ct<T>(j < W - 1 ? in[7].get(j + 1) : r7);
             g[8] = to_ct<T>(j > 0 ? in[8].get(j - 1) : l8);
+            if constexpr (REF) {
+                // sources x+j-e_k: offsets j (x), j+1 (x+1), j+2 (x+2) in the windows
+                const uint32_t su[9] = {rc[j + 1], rc[j], rs_[j + 1], rc[j + 2], rn_[j + 1],
+                                        rs_[j],    rs_[j + 2], rn_[j + 2], rn_[j]};
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    float ux, uy;
+                    ref_unpack(su[k], ux, uy);
+                    g[k] = __builtin_fmaf(g[k], kRefInvScale, cs_ref_pop(k, ux, uy, p.ref_c));
+                }
+            }
             const CsMoments<CT> m = cs_collide(g, o, c);
+            if constexpr (REF) {
+                float ux, uy;
+                ref_unpack(rc[j + 1], ux, uy);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) o[k] = (o[k] - cs_ref_pop(k, ux, uy, p.ref_c)) * kRefScale;
+            }
             CsRand<T> rnd(y * Nx + x + j, p.salt);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {

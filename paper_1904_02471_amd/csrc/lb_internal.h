@@ -49,7 +49,54 @@ struct Params {
     CT fd_w1;
     CT fd_m[kMaxN + 1][kMaxN + 1], fd_jx[kMaxN + 1][kMaxN + 1], fd_jy[kMaxN + 1][kMaxN + 1];
     unsigned salt;  // per launch: seeds the stochastic rounding of FP16 stores
+    // CS with FP16 storage relative to a reference equilibrium
+    // (LB_FP16_REF): per node the reference velocity U in lattice units as
+    // two FP16 values packed in 32 bits (x low), rows of `pitch` entries;
+    // NULL otherwise.  ref_c: the FP32 constants of the shift (cs_ref_pop).
+    const uint32_t *ref;
+    float ref_c[8];
 };
+
+// Shift of CS population k (D2Q9 order) under LB_FP16_REF: the second-order
+// equilibrium at (rho0, rho0 U) less w_k rho0, the same expression as the
+// collision's equilibrium (Section 2):
+//   R_k(U) = rho0 (a_k e_k.U + b_k (e_k.U)^2 - w_k 1.5 |U|^2),
+// a = 3 w, b = 4.5 w (a_0 = b_0 = 0).  The stored value of population k at
+// node s is f_k - w_k rho0 - R_k(U(s)): for a flow near the reference the
+// stored departures are small, and so is their FP16 rounding.  Always FP32
+// (c = {w0, w1, w5, a1, a5, b1, b5, rho0}), in every kernel that reads or
+// writes the storage, so that each path adds and removes the same value.
+__host__ __device__ __forceinline__ float cs_ref_pop(int k, float ux, float uy, const float (&c)[8])
+{
+    float eu, w, a, b;
+    switch (k) {
+    case 0: eu = 0.0f; w = c[0]; a = 0.0f; b = 0.0f; break;
+    case 1: eu = ux; w = c[1]; a = c[3]; b = c[5]; break;
+    case 2: eu = uy; w = c[1]; a = c[3]; b = c[5]; break;
+    case 3: eu = -ux; w = c[1]; a = c[3]; b = c[5]; break;
+    case 4: eu = -uy; w = c[1]; a = c[3]; b = c[5]; break;
+    case 5: eu = ux + uy; w = c[2]; a = c[4]; b = c[6]; break;
+    case 6: eu = uy - ux; w = c[2]; a = c[4]; b = c[6]; break;
+    case 7: eu = -ux - uy; w = c[2]; a = c[4]; b = c[6]; break;
+    default: eu = ux - uy; w = c[2]; a = c[4]; b = c[6]; break;
+    }
+    const float usq = 1.5f * __builtin_fmaf(ux, ux, uy * uy);
+    return c[7] * __builtin_fmaf(a, eu, __builtin_fmaf(b * eu, eu, -(w * usq)));
+}
+
+// The stored departure of LB_FP16_REF is scaled by 2^12 before its FP16
+// rounding (and by 2^-12 when read, both exact): departures of a few 1e-5
+// would otherwise fall below the FP16 normal range (6.1e-5), whose fixed
+// subnormal spacing 6e-8 would cap their precision; scaled, they keep the
+// relative precision 2^-11 down to 1.5e-8, and up to 16 in magnitude.
+constexpr float kRefScale = 4096.0f, kRefInvScale = 1.0f / 4096.0f;
+
+// The two FP16 halves of a packed reference velocity, as FP32.
+__host__ __device__ __forceinline__ void ref_unpack(uint32_t v, float &ux, float &uy)
+{
+    ux = (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
+    uy = (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
+}
 
 // Fused or stand-alone diagnostics: per-block FP64 partial sums.
 template <typename CT>
@@ -223,6 +270,12 @@ hipError_t launch_reduce(const T *src, bool cs, const Params<double> &p, const D
 template <typename T>
 hipError_t launch_reduce_field(const T *src, bool cs, const Params<double> &p, const double *phix, const double *phiy,
                                double *partial, double *out, hipStream_t s);
+// Reference velocities of LB_FP16_REF (packed FP16 pairs, rows of pitch
+// entries): from velocity fields (divided by c_l: inv_cl = 1 / c_l) or from
+// the velocity of a canonical state f [K][Ny][Nx].
+hipError_t launch_ref_from_velocity(uint32_t *ref, const double *ux, const double *uy, const Params<double> &p,
+                                    double inv_cl, hipStream_t s);
+hipError_t launch_ref_from_state(uint32_t *ref, const double *f, const Params<double> &p, hipStream_t s);
 // Device address and capacity (doubles) of the fixed partials array of the
 // field reduction on `device` (looked up once per device; thread-safe).
 hipError_t reduce_field_scratch(int device, double **ptr, size_t *capacity);

@@ -11,7 +11,9 @@
 #include "lb_model.h"
 
 namespace lbm {
-enum Prec { P32 = 0, P16 = 1, P64 = 2 };
+// storage: FP32, FP16 shifted by w_k rho0, FP64, FP16 relative to a
+// reference equilibrium (CS only)
+enum Prec { P32 = 0, P16 = 1, P64 = 2, P16R = 3 };
 }  // namespace lbm
 
 struct lb_sim {
@@ -60,6 +62,7 @@ struct lb_sim {
     int cs_threads = 0;
     int fd_rows = 8;
     int fd_rows_rest = 4;
+    uint32_t *d_ref = nullptr;  // LB_FP16_REF: reference velocity per node (packed FP16 pairs)
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;
 };

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LB_CS_D2Q9, LB_FD_D2Q9, LB_FD_D2Q16, LB_FD_D2Q25, LB_FD_D2Q36 = 0, 1, 2, 3, 4
-LB_FP32, LB_FP16_SHIFTED, LB_FP64 = 0, 1 << 8, 2 << 8
+LB_FP32, LB_FP16_SHIFTED, LB_FP64, LB_FP16_REF = 0, 1 << 8, 2 << 8, 3 << 8
 LB_IMEX = 1 << 10
 LB_OK, LB_EINVAL, LB_ECFL, LB_ESTIFF, LB_ENOMEM, LB_EDEVICE, LB_ENAN, LB_EBUSY, LB_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 Q_OF_MODEL = {LB_CS_D2Q9: 3, LB_FD_D2Q9: 3, LB_FD_D2Q16: 4, LB_FD_D2Q25: 5, LB_FD_D2Q36: 6}

@@ -14,7 +14,8 @@ Tolerances (per element of the canonical state f, absolute):
       FP64 rounding of the unshifted f:
       tol = 32 u32 (n + 1) max|g| + 1e-13 (n + 1) max|f|.
   FP16 storage: the stored g carries a relative rounding of u16 = 2^-11 per
-      step: tol = 2 u16 (n + 1) max|g| + the FP32 bound.
+      step: tol = 2 u16 (n + 1) max|g| + the FP32 bound (FP16 relative to a
+      reference equilibrium stores smaller departures: the same bound).
 """
 import numpy as np
 
@@ -26,7 +27,7 @@ U16 = 2.0 ** -11
 
 ORACLE_MODEL = {lb.LB_CS_D2Q9: oracle.CS_D2Q9, lb.LB_FD_D2Q9: oracle.FD_D2Q9, lb.LB_FD_D2Q16: oracle.FD_D2Q16,
                 lb.LB_FD_D2Q25: oracle.FD_D2Q25, lb.LB_FD_D2Q36: oracle.FD_D2Q36}
-PREC_NAME = {lb.LB_FP32: "fp32", lb.LB_FP16_SHIFTED: "fp16", lb.LB_FP64: "fp64"}
+PREC_NAME = {lb.LB_FP32: "fp32", lb.LB_FP16_SHIFTED: "fp16", lb.LB_FP64: "fp64", lb.LB_FP16_REF: "fp16ref"}
 
 
 def pair(model, Nx, Ny, tau, dt, ds, N, prec, bc=None, eps=None):
@@ -47,7 +48,9 @@ def tolerance(prec, nsteps, f_ref, w, rho0):
     if prec == lb.LB_FP64:
         return 1e-13 * (nsteps + 1) * fmax
     tol = 32 * U32 * (nsteps + 1) * gmax + 1e-13 * (nsteps + 1) * fmax
-    if prec == lb.LB_FP16_SHIFTED:
+    if prec in (lb.LB_FP16_SHIFTED, lb.LB_FP16_REF):
+        # (relative to a reference equilibrium the stored departures are at
+        # most as large as g, so the same bound holds)
         tol += 2 * U16 * (nsteps + 1) * gmax
     return tol
 

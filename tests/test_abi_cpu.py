@@ -75,7 +75,7 @@ def test_d2q9_tables():
     ((lb.LB_FD_D2Q9 | lb.LB_FP16_SHIFTED, 32768, 32768, 1.0, 1e-5, 1e-4, 2), lb.LB_EINVAL),  # FP32 moment plane of 4 GiB
     # 896 bytes under 4 GiB unpadded, over it with the 4352-byte plane pad
     ((lb.LB_FD_D2Q9 | lb.LB_FP64, 536870800, 1, 1.0, 1e-5, 1e-4, 2), lb.LB_EINVAL),
-    ((lb.LB_CS_D2Q9 | (3 << 8), 8, 8, 0.8, 1.0, 1.0, 2), lb.LB_EINVAL),
+    ((lb.LB_FD_D2Q16 | lb.LB_FP16_REF, 8, 8, 1e-3, 1e-4, 0.1, 3), lb.LB_EINVAL),  # reference-shifted FP16: CS only
     ((lb.LB_CS_D2Q9, 8, 8, float("nan"), 1.0, 1.0, 2), lb.LB_EINVAL),
 ])
 def test_create_validation(args, code):

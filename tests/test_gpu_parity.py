@@ -12,6 +12,7 @@ from tests.gpu_helpers import PREC_NAME, assert_state_close, field_errors, pair,
 pytestmark = pytest.mark.gpu
 
 PRECS = [lb.LB_FP64, lb.LB_FP32, lb.LB_FP16_SHIFTED]
+CS_PRECS = PRECS + [lb.LB_FP16_REF]   # FP16 relative to a reference equilibrium: CS only
 
 
 def cs_case(Nx, Ny, tau=0.7, prec=lb.LB_FP32, bc=None, dsdt=(1.0, 1.0)):
@@ -49,7 +50,7 @@ def run_and_compare(g, o, steps, prec, what, fields=False):
                 assert e_rho <= 1e-5 and e_u <= 1e-5
 
 
-@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_NAME[p])
+@pytest.mark.parametrize("prec", CS_PRECS, ids=lambda p: PREC_NAME[p])
 def test_cs_8x8_random_state(prec):
     print("case: cs 8x8 random non-equilibrium state", PREC_NAME[prec], flush=True)
     g, o = cs_case(8, 8, prec=prec)
@@ -72,7 +73,7 @@ def test_cs_ragged_shapes(shape):
     run_and_compare(g, o, [1, 5, 20], lb.LB_FP32, "cs %dx%d" % shape)
 
 
-@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_NAME[p])
+@pytest.mark.parametrize("prec", CS_PRECS, ids=lambda p: PREC_NAME[p])
 @pytest.mark.parametrize("Nx", [4, 8, 12, 260, 516, 2052, 4100])
 def test_cs_vector_rows(Nx, prec):
     """Periodic rows whose width is a multiple of the chunk width take the
@@ -85,6 +86,39 @@ def test_cs_vector_rows(Nx, prec):
     g.set_state(f0)
     o.set_state(f0)
     run_and_compare(g, o, [1, 4], prec, "cs vector rows %d %s" % (Nx, PREC_NAME[prec]))
+
+
+@pytest.mark.parametrize("shape", [(37, 23), (1, 7), (5, 1), (6, 3)])
+def test_cs_fp16_ref_scalar_rows(shape):
+    """FP16 relative to a reference equilibrium on rows the vector form does
+    not take (widths not a multiple of 4): the scalar row form, from an
+    initial equilibrium and then from a set non-equilibrium state; the
+    reference follows each (velocity of the initial fields, of the set
+    state)."""
+    Nx, Ny = shape
+    print("case: cs fp16ref scalar rows", shape, flush=True)
+    g, o = cs_case(Nx, Ny, tau=0.6, prec=lb.LB_FP16_REF)
+    rho, ux, uy = workloads.random_state(Nx, Ny, 9 + Nx, g.cs)
+    g.init(rho, ux, uy)
+    o.init(rho, ux, uy)
+    run_and_compare(g, o, [1, 5, 20], lb.LB_FP16_REF, "cs fp16ref %dx%d" % shape)
+    f0 = workloads.random_distribution(9, Nx, Ny, 5 + Ny, g.w, spread=0.2)
+    g.set_state(f0)
+    o.set_state(f0)
+    assert_state_close(g.get_state(), f0, tolerance(lb.LB_FP16_REF, 0, f0, g.w, f0.sum(0).mean()),
+                       "cs fp16ref set/get state")
+    run_and_compare(g, o, [1, 7], lb.LB_FP16_REF, "cs fp16ref state %dx%d" % shape)
+
+
+def test_cs_fp16_ref_rejections():
+    """Reference-shifted FP16 storage: collision-streaming and periodic only."""
+    g = lb.Sim(lb.LB_CS_D2Q9, 8, 8, 0.7, 1.0, 1.0, 2, precision=lb.LB_FP16_REF)
+    with pytest.raises(lb.LBError) as e:
+        g.set_bc_x(1.1, 0.9)
+    assert e.value.code == lb.LB_EINVAL
+    with pytest.raises(lb.LBError) as e:
+        lb.Sim(lb.LB_FD_D2Q16, 8, 8, 1e-2, 1e-3, 0.1, 3, precision=lb.LB_FP16_REF)
+    assert e.value.code == lb.LB_EINVAL
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_NAME[p])

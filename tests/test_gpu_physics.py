@@ -145,27 +145,56 @@ def test_taylor_green_4096_fp32():
     assert nu_fit == pytest.approx(nu, rel=1e-3)
 
 
-def test_taylor_green_4096_fp16():
-    """FP16-shifted storage with stochastic rounding, six independent
-    realisations of the rounding (seeds 0-5).  The vortex decays by 4e-4 over
-    the run, ~8e-8 per step, while one FP16 ulp of the stored populations is
-    ~5e-4 of them: round-to-nearest freezes the state between ulps (fitted nu
-    15% off, the same every run).  Stochastic rounding is unbiased, and what
-    is left is its noise: ~1e-6 of momentum per node and step, which the
-    vortex integrates as a random walk; over 5000 steps the fitted nu of one
-    run scatters by ~7e-3 (relative standard deviation over 8 seeds).  Bounds:
-    the mean over the six runs within 1e-2 (3.7 standard errors) and every run
-    within 3e-2 (4.5 standard deviations); the FP32 storage case above meets
-    1e-3 in one run."""
+def fp16_nu_errors(prec, seeds=range(6)):
     errs = []
-    for seed in range(6):
-        print("case: tgv 4096 fp16 seed", seed, flush=True)
-        nu_fit, nu = tgv4096_nu(lb.LB_FP16_SHIFTED, seed)
+    for seed in seeds:
+        print("case: tgv 4096 %s seed %d" % ("fp16ref" if prec == lb.LB_FP16_REF else "fp16", seed), flush=True)
+        nu_fit, nu = tgv4096_nu(prec, seed)
         errs.append(nu_fit / nu - 1)
-        print("nu fp16 seed %d: %.7f analytic %.7f (rel %+.2e)" % (seed, nu_fit, nu, errs[-1]), flush=True)
+        print("seed %d: nu %.7f analytic %.7f (rel %+.2e)" % (seed, nu_fit, nu, errs[-1]), flush=True)
     print("mean rel error %+.2e, std %.2e" % (np.mean(errs), np.std(errs, ddof=1)), flush=True)
-    assert abs(np.mean(errs)) < 1e-2
-    assert max(abs(e) for e in errs) < 3e-2
+    return np.array(errs)
+
+
+def test_taylor_green_4096_fp16_ref():
+    """FP16 storage relative to the vortex's initial equilibrium (40 bytes per
+    node-step), six realisations of the stochastic rounding: every fitted nu
+    within the 1e-3 target.  The stored departures from the reference are
+    ~1e-5 where the shifted populations are ~3e-3, and the rounding noise
+    that the vortex amplitude integrates shrinks with them."""
+    errs = fp16_nu_errors(lb.LB_FP16_REF)
+    assert np.max(np.abs(errs)) < 1e-3
+
+
+def test_taylor_green_4096_fp16_shifted_unbiased():
+    """FP16 storage shifted by w_k rho0 (36 bytes per node-step), six
+    realisations of the stochastic rounding (seeds 0-5).  The vortex decays
+    by 4e-4 over the run, ~8e-8 per step, while one FP16 step of the stored
+    populations (|g| ~ 3e-3) is ~5e-4 of them: round-to-nearest would freeze
+    the state; stochastic rounding is unbiased, and what is left is its
+    noise, ~1e-6 of momentum per node and step, which the vortex integrates
+    as a random walk: the fitted nu of one run scatters by ~7e-3 (relative
+    standard deviation).  Checked here: no bias (the mean of the six runs
+    within 3 standard errors of the FP32-storage fit) and a spread of that
+    size (below 2e-2).  The 1e-3 target of a single run is met by the
+    reference-shifted storage above, not by this one
+    (test_taylor_green_4096_fp16_shifted_target)."""
+    errs = fp16_nu_errors(lb.LB_FP16_SHIFTED)
+    nu32, nu = tgv4096_nu(lb.LB_FP32)
+    e32 = nu32 / nu - 1
+    sd = np.std(errs, ddof=1)
+    print("fp32 rel error %+.2e; fp16 mean %+.2e, standard error %.2e" % (e32, np.mean(errs), sd / np.sqrt(6)),
+          flush=True)
+    assert abs(np.mean(errs) - e32) < 3 * sd / np.sqrt(len(errs))
+    assert sd < 2e-2
+
+
+@pytest.mark.skip(reason="unmet: FP16 storage shifted by w_k rho0 scatters the fitted nu of one 4096^2 "
+                         "Taylor-Green run by ~7e-3 (stochastic-rounding noise integrated by the vortex); "
+                         "LB_FP16_REF meets the 1e-3 target (test_taylor_green_4096_fp16_ref)")
+def test_taylor_green_4096_fp16_shifted_target():
+    errs = fp16_nu_errors(lb.LB_FP16_SHIFTED)
+    assert np.max(np.abs(errs)) < 1e-3
 
 
 def test_taylor_green_2048_fd_d2q36():
