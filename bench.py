@@ -63,6 +63,9 @@ def parse():
                     help="time one model alone (profiling runs); the JSON line is then per model")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of the CS state size (counter calibration)")
+    ap.add_argument("--fd-fused", type=int, default=-1,
+                    help="FD step form after autotuning: -1 the tuner's choice, 0 the three stage launches, "
+                         "R > 0 the temporally blocked step with R-row segments (profiling runs)")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving stream to replay (0: skip; 512: the whole stream)")
     return ap.parse_args()
@@ -153,6 +156,45 @@ def fd_d2q36(lb, workloads, units, stream, n=2048, steps=20, warmup=3):
             "mlups": round(n * n / (ms * 1e-3) / 1e6, 1), "achieved_gbs_stagewise": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node_step": 8 * 36 * 4,
             "fd_tile_rows": shapes[1], "fd_tile_rows_later_stages": shapes[2]}
+
+
+def fd_fused_compare(lb, workloads, units, stream, n=2048, steps=20, warmup=3):
+    """FD D2Q16 (N = 3) plain steps on the n x n vortex of the benchmark: the
+    three stage launches (autotuned tiles) against the temporally blocked
+    step with 32-, 64- and 128-row segments; MLUPS and the HBM rate of each
+    form's algorithmic bytes (stage launches 8 K s per step, fused 2 K s plus
+    the moment planes).  D2Q36 has no fused form (its register windows do not
+    fit), so only D2Q9/D2Q16 are timed."""
+    import torch
+    ds = 1.0 / n
+    tau = units.tau_fd_from_std(0.6, n)
+    vmax = lb.lb_model_info(lb.LB_FD_D2Q16)[0].max()
+    dt = units.fd_time_step(tau, ds, vmax, 0.5)
+    sim = lb.Sim(lb.LB_FD_D2Q16, n, n, tau, dt, ds, 3, precision=lb.LB_FP32)
+    sim.set_stream(stream.cuda_stream)
+    r, ux, uy, _ = workloads.taylor_green(n, n, units.velocity_fd_from_std(0.01), 1.0)
+    sim.init(r, ux, uy)
+    del r, ux, uy
+    sim.autotune(3)
+    out = {"grid": [n, n], "steps": steps}
+    for name, ys in (("stage_launches", 0), ("fused_ys32", 32), ("fused_ys64", 64), ("fused_ys128", 128)):
+        sim.set_fd_fused(ys)
+        sim.step(warmup)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            sim.step(steps)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        bpn = 512 if ys == 0 else 2 * 16 * 4 + 24
+        gbs = bpn * n * n / (ms * 1e-3) / 1e9
+        out[name] = {"ms_per_step": round(ms, 5), "mlups": round(n * n / (ms * 1e-3) / 1e6, 1),
+                     "bytes_per_node_step": bpn, "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    sim.destroy()
+    out["fd_d2q36"] = "stage launches only: 36 populations of register windows exceed the register file"
+    return out
 
 
 def source_digest(files):
@@ -385,7 +427,11 @@ def main():
     fd.series_reserve(cap)
     # launch shapes of the plain steps chosen by the library's autotuner
     fd_tuned = fd.autotune(5)
-    tuned = {"cs_threads": cs.autotune(10)[0], "fd_tile_rows": fd_tuned[1], "fd_tile_rows_later_stages": fd_tuned[2]}
+    if args.fd_fused >= 0:
+        fd.set_fd_fused(args.fd_fused)
+    tuned = {"cs_threads": cs.autotune(10)[0], "fd_tile_rows": fd_tuned[1], "fd_tile_rows_later_stages": fd_tuned[2],
+             "fd_fused_segment_rows": fd.fd_fused()}
+    fused = fd.fd_fused() > 0
     run_cs = args.only in (None, "cs")
     run_fd = args.only in (None, "fd")
 
@@ -432,9 +478,12 @@ def main():
     nodes = n * n
     ms_per_step = wall * 1e3 / K
     bytes_cs = 2 * 9 * 4 * nodes                 # read + write 9 FP32 values per node
-    bytes_fd_stage = (8 * 16 * 4 * nodes) / 3.0  # 8 K s per step over 3 stage launches
+    # FD: three stage launches move 8 K s per step (8/3 K s per launch); the
+    # fused step reads the state and its three moment planes once and writes
+    # them once: (2 K s + 6 x 4) per step, one launch
+    bytes_fd_stage = (8 * 16 * 4 * nodes) / 3.0 if not fused else (2 * 16 * 4 + 24) * nodes
     cs_gbs = bytes_cs / (cs_ms * 1e-3) / 1e9 if run_cs else 0.0
-    fd_stage_ms = fd_ms / 3.0
+    fd_stage_ms = fd_ms / 3.0 if not fused else fd_ms
     fd_gbs = bytes_fd_stage / (fd_stage_ms * 1e-3) / 1e9 if run_fd else 0.0
     value = nodes / (ms_per_step * 1e-3) / 1e6
 
@@ -466,8 +515,9 @@ def main():
                     "bytes_per_node_step": 72},
         "fd_d2q16": {"ms_per_step": round(fd_ms, 5),
                      "mlups": round(nodes / (fd_ms * 1e-3) / 1e6, 1) if run_fd else None,
-                     "achieved_gbs_stagewise": round(fd_gbs, 1), "hbm_frac": round(fd_gbs / HBM_PEAK_GBS, 4),
-                     "bytes_per_node_step": 512},
+                     "kernel": "fd_fused_step_kernel" if fused else "fd_stage_kernel (3 launches)",
+                     "achieved_gbs": round(fd_gbs, 1), "hbm_frac": round(fd_gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_node_step": 152 if fused else 512},
     }
     if run_fd:
         # The FD stage dominates the step.  Its two roofs, both against
@@ -476,7 +526,7 @@ def main():
         # algorithmic flops).  The binding roof is the one with the higher
         # fraction.  Launch duration: the FD step time over its three stage
         # launches (events on the launch stream around the FD steps).
-        flops_launch = nodes * (16 * sum(FD16_FLOPS_NODE_POP) / 3.0 + FD16_FLOPS_NODE)
+        flops_launch = nodes * (16 * sum(FD16_FLOPS_NODE_POP) / 3.0 + FD16_FLOPS_NODE) * (3 if fused else 1)
         tflops = flops_launch / (fd_stage_ms * 1e-3) / 1e12
         hbm_frac = fd_gbs / HBM_PEAK_GBS
         alu_frac = tflops / VALU_PEAK_PUBLISHED_TFLOPS
@@ -486,8 +536,9 @@ def main():
         else:
             roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_PUBLISHED_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+        kname = "fd_fused_step_kernel" if fused else "fd_stage_kernel"
         line["roofline"] = dict(
-            kernel="fd_stage_kernel", **roof, traffic=kernel_traffic("fd_stage_kernel", n),
+            kernel=kname, **roof, traffic=kernel_traffic(kname, n),
             bytes_per_launch=bytes_fd_stage, flops_per_launch=flops_launch,
             hbm_frac=round(hbm_frac, 4), alu_frac_published_peak=round(alu_frac, 4),
             alu_tflops=round(tflops, 2),
@@ -516,6 +567,7 @@ def main():
         fd.destroy()
         line["cs_d2q9_4096"] = cache_free_cs(lb, workloads, stream)
         line["fd_d2q36"] = fd_d2q36(lb, workloads, units, stream)
+        line["fd_d2q16_fused_vs_stages"] = fd_fused_compare(lb, workloads, units, stream)
     if args.serving_requests > 0:
         if args.only is not None or args.no_cache_free:
             cs.destroy()

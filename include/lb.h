@@ -259,7 +259,9 @@ int lb_set_rounding_seed(lb_sim *sim, unsigned seed);
  * 512 and 1024 threads against one chunk per thread; FD tiles of 64 x 32 and
  * 64 x 16 nodes, chosen separately for the first Runge-Kutta stage and for
  * the later stages (which also read the step's base state, so their kernels
- * hold more registers and LDS).  Synchronises the stream.  LB_ESTATE before
+ * hold more registers and LDS), then, where lb_set_fd_fused applies, the
+ * three stage launches against the fused step with 32-, 64- and 128-row
+ * segments.  Synchronises the stream.  LB_ESTATE before
  * lb_init, LB_EINVAL for reps outside [1, 1000]. */
 int lb_autotune(lb_sim *sim, int reps);
 
@@ -269,6 +271,22 @@ int lb_autotune(lb_sim *sim, int reps);
  * tiles) or 4 (64 x 16).  LB_EINVAL otherwise.  Defaults of a new handle:
  * 0, 8, 4. */
 int lb_set_tuning(lb_sim *sim, int cs_threads, int fd_rows, int fd_rows_rest);
+
+/* FD plain steps by the temporally blocked kernel: the three Runge-Kutta
+ * stages of a step in one launch (Section 2), each workgroup marching up a
+ * y-segment of rows_per_segment rows of an x-strip of 110 columns with the
+ * stage values kept on chip; the new state is bit for bit that of the three
+ * stage launches, with the state read once (plus halos) and written once per
+ * step instead of eight state transfers.  0 (the default of a new handle)
+ * restores the stage launches; lb_autotune chooses between them.  FP32
+ * storage, periodic, Q = 3 or 4 (D2Q9, D2Q16), explicit Runge-Kutta only:
+ * LB_EINVAL otherwise, and for values outside [0, 4096].  Sampled steps keep
+ * the stage launches (their first stage sums the diagnostics). */
+int lb_set_fd_fused(lb_sim *sim, int rows_per_segment);
+
+/* Segment rows of the fused FD step, 0 for the stage launches (LB_EINVAL for
+ * a NULL handle). */
+int lb_get_fd_fused(const lb_sim *sim);
 
 /* The current plain-step launch shapes (host ints). */
 int lb_get_tuning(const lb_sim *sim, int *cs_threads, int *fd_rows, int *fd_rows_rest);

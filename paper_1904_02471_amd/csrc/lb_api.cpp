@@ -199,6 +199,12 @@ int dev_status(hipError_t e) { return e == hipSuccess ? LB_OK : (e == hipErrorOu
 // Current canonical-state buffer.
 int state_index(const lb_sim *s) { return s->cs ? s->cur : 0; }
 
+// Whether plain FD steps take the temporally blocked kernel.
+bool fused_active(const lb_sim *s)
+{
+    return !s->cs && !s->imex && s->prec == P32 && s->fd_fused_ys > 0 && fd_fused_supported(s->Q, s->fixed);
+}
+
 // Advance one step; diag non-null fuses the diagnostics of the input state.
 template <typename T>
 hipError_t step_once(lb_sim *s, bool with_diag)
@@ -221,7 +227,7 @@ hipError_t step_once(lb_sim *s, bool with_diag)
         }
     }
     const DiagArgs<CT> *dp = with_diag ? &d : nullptr;
-    hipError_t e;
+    hipError_t e = hipSuccess;
     if (s->cs) {
         e = launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, dp, s->stream, s->cs_threads);
         s->cur ^= 1;
@@ -236,6 +242,12 @@ hipError_t step_once(lb_sim *s, bool with_diag)
             if (e == hipSuccess) e = launch_fd_stage<T>(a, nullptr, b, 1, p, dp, s->stream, dp ? 8 : s->fd_rows);
             if (e == hipSuccess) e = launch_fd_imex<T>(1, a, g, b, p, r, s->stream);
             if (e == hipSuccess) e = launch_fd_stage<T>(b, a, g, 4, p, nullptr, s->stream, s->fd_rows_rest);
+        } else if (std::is_same<T, float>::value && !dp && fused_active(s)) {
+            // the three stages in one launch into A, which becomes the state
+            if constexpr (std::is_same<T, float>::value) {
+                e = launch_fd_fused(g, a, p, s->fd_fused_ys, s->stream);
+                if (e == hipSuccess) std::swap(s->buf[0], s->buf[1]);
+            }
         } else {
             e = launch_fd_stage<T>(g, nullptr, a, 1, p, dp, s->stream, dp ? 8 : s->fd_rows);
             if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, s->fd_rows_rest);
@@ -248,8 +260,9 @@ hipError_t step_once(lb_sim *s, bool with_diag)
 
 // ---------------------------------------------------------------------
 // Graph replay of plain steps.  The kernel arguments of a run of steps
-// without sampling repeat exactly (CS: after an even number of steps the
-// ping-pong pair is back at its start; FD: the buffers never move), so a
+// without sampling repeat exactly (CS, and FD with the fused kernel: after an
+// even number of steps the ping-pong pair is back at its start; FD stage
+// launches: the buffers never move), so a
 // captured graph of G steps replays any run of G steps with one launch.
 // FP16 storage is excluded: its stochastic rounding draws fresh random bits
 // every step, which a replayed graph would repeat.
@@ -257,7 +270,9 @@ int graph_len(const lb_sim *s)
 {
     if (s->prec == P16 || s->prec == P16R) return 0;
     int g = s->graph_steps < 0 ? (s->cs ? 8 : 4) : s->graph_steps;
-    if (s->cs && (g & 1)) ++g;
+    // CS, and FD with the fused kernel: the two state buffers alternate, so
+    // a replayed run must return them to their start
+    if ((s->cs || fused_active(s)) && (g & 1)) ++g;
     return g;
 }
 
@@ -339,6 +354,27 @@ hipError_t time_candidate(lb_sim *s, int cs_threads, int fd_stage, int fd_rows, 
     if (e == hipSuccess) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
     for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return e;
+}
+
+// Time `reps` launches of the temporally blocked FD step from the state into
+// buffer A (which the next step overwrites; the state is untouched).
+hipError_t time_fused(lb_sim *s, int ys, int reps, float *ms)
+{
+    const Params<float> p = make_params<float>(s);
+    const float *g = bufp<float>(s, 0);
+    float *a = bufp<float>(s, 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_fd_fused(g, a, p, ys, s->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_fd_fused(g, a, p, ys, s->stream);
     if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -842,11 +878,30 @@ int lb_autotune(lb_sim *s, int reps)
         e = pick({8, 4}, 1, &rows1);
         if (e == hipSuccess) e = pick({8, 4}, 2, &rows_rest);
     }
+    // FD: the stage launches (stage 1 + twice a later stage, with the tile
+    // heights just chosen) against the temporally blocked kernel with
+    // y-segments of 32, 64 and 128 rows
+    int fused = 0;
+    if (e == hipSuccess && !s->cs && !s->imex && s->prec == P32 && fd_fused_supported(s->Q, s->fixed)) {
+        float t1 = 0.0f, t2 = 0.0f;
+        e = time_candidate<float>(s, 0, 1, rows1, reps, &t1);
+        if (e == hipSuccess) e = time_candidate<float>(s, 0, 2, rows_rest, reps, &t2);
+        float best = t1 + 2.0f * t2;
+        for (int ys : {32, 64, 128}) {
+            float tf = 0.0f;
+            if (e == hipSuccess) e = time_fused(s, ys, reps, &tf);
+            if (e == hipSuccess && tf < best) {
+                best = tf;
+                fused = ys;
+            }
+        }
+    }
     if (e != hipSuccess) return fail(dev_status(e));
     drop_graphs(s);
     s->cs_threads = cs_threads;
     s->fd_rows = rows1;
     s->fd_rows_rest = rows_rest;
+    s->fd_fused_ys = fused;
     return LB_OK;
 }
 
@@ -871,6 +926,19 @@ int lb_get_tuning(const lb_sim *s, int *cs_threads, int *fd_rows, int *fd_rows_r
     *fd_rows_rest = s->fd_rows_rest;
     return LB_OK;
 }
+
+int lb_set_fd_fused(lb_sim *s, int rows_per_segment)
+{
+    if (!s || rows_per_segment < 0 || rows_per_segment > 4096) return fail(LB_EINVAL);
+    if (rows_per_segment > 0 && (s->cs || s->imex || s->prec != P32 || !fd_fused_supported(s->Q, s->fixed)))
+        return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    drop_graphs(s);
+    s->fd_fused_ys = rows_per_segment;
+    return LB_OK;
+}
+
+int lb_get_fd_fused(const lb_sim *s) { return s ? s->fd_fused_ys : fail(LB_EINVAL); }
 
 int lb_set_rounding_seed(lb_sim *s, unsigned seed)
 {

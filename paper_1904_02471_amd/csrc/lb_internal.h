@@ -235,6 +235,12 @@ hipError_t launch_cs_step(const T *src, T *dst, const Params<typename Arith<T>::
 template <typename T>
 hipError_t launch_fd_stage(const T *src, const T *gn, T *out, int stage, const Params<typename Arith<T>::type> &p,
                            const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int rows = 8);
+// Temporally blocked FD step (lb_fd_fused.hip): the three Runge-Kutta stages
+// in one launch, src (state with its moment planes) -> dst; strips of 110
+// output columns, y-segments of Ys rows.  FP32 storage, periodic, Q = 3 or 4
+// (fd_fused_supported); the output is bitwise that of the stage launches.
+bool fd_fused_supported(int Q, bool fixed);
+hipError_t launch_fd_fused(const float *src, float *dst, const Params<float> &p, int Ys, hipStream_t s);
 // Pointwise stages of the implicit-explicit FD step: which = 0 relaxes g
 // into a_buf; which = 1 turns (y in b_buf, g, f1 in a_buf) into (f2 in
 // b_buf, the last stage's base in a_buf).  dt_over_tau = dt / tau.

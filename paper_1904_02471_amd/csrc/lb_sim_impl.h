@@ -62,6 +62,9 @@ struct lb_sim {
     int cs_threads = 0;
     int fd_rows = 8;
     int fd_rows_rest = 4;
+    // FD plain steps by the temporally blocked kernel with y-segments of this
+    // many rows (0: three stage launches); FP32, periodic, Q = 3 or 4
+    int fd_fused_ys = 0;
     uint32_t *d_ref = nullptr;  // LB_FP16_REF: reference velocity per node (packed FP16 pairs)
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;

@@ -25,6 +25,7 @@ EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_
            "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
            "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_rounding_seed", "lb_autotune", "lb_set_tuning",
+           "lb_set_fd_fused", "lb_get_fd_fused",
            "lb_get_tuning", "lb_set_stream", "lb_synchronize",
            "lb_device_bytes",
            "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
@@ -71,6 +72,8 @@ def _load():
         "lb_set_rounding_seed": (ctypes.c_int, [_vp, ctypes.c_uint]),
         "lb_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "lb_set_fd_fused": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_get_fd_fused": (ctypes.c_int, [_vp]),
         "lb_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
         "lb_set_stream": (ctypes.c_int, [_vp, _vp]),
@@ -251,6 +254,14 @@ class Sim:
         later stages (default: the same)."""
         rest = fd_rows if fd_rows_rest is None else fd_rows_rest
         _check(_lib.lb_set_tuning(self._h, int(cs_threads), int(fd_rows), int(rest)), "lb_set_tuning")
+
+    def set_fd_fused(self, rows_per_segment):
+        """FD plain steps by the temporally blocked kernel with y-segments of
+        this many rows (0: the three stage launches)."""
+        _check(_lib.lb_set_fd_fused(self._h, int(rows_per_segment)), "lb_set_fd_fused")
+
+    def fd_fused(self):
+        return _lib.lb_get_fd_fused(self._h)
 
     def tuning(self):
         """(cs_threads, fd_rows, fd_rows_rest) of the plain steps."""
