@@ -206,11 +206,12 @@ def source_digest(files):
     return h.hexdigest()
 
 
-def kernel_traffic(kernel, n):
-    """HBM bytes per launch of `kernel` on the n x n workload from the
-    calibrated FETCH_SIZE + WRITE_SIZE counters recorded in
-    paper_1904_02471_amd/kernel_traffic.json, or None when none were recorded
-    for this workload or the kernel's sources changed since."""
+def kernel_record(kernel, n, shape=None):
+    """The counter record of `kernel` on the n x n workload in
+    paper_1904_02471_amd/kernel_traffic.json (calibrated FETCH_SIZE +
+    WRITE_SIZE bytes and SQ_INSTS_VALU per launch), or None when none was
+    recorded for this workload and launch shape, or the kernel's sources
+    changed since."""
     path = os.path.join(ROOT, "paper_1904_02471_amd", "kernel_traffic.json")
     if not os.path.exists(path):
         return None
@@ -218,7 +219,19 @@ def kernel_traffic(kernel, n):
         rec = json.load(fh).get(kernel)
     if not rec or rec.get("grid") != [n, n] or rec.get("sources_sha256") != source_digest(rec["sources"]):
         return None
-    return rec["bytes_per_launch"]
+    for key, want in (shape or {}).items():
+        if rec.get(key) != want:
+            return None
+    return rec
+
+
+def valu_issue(rec, launch_ms):
+    """Fraction of the vector-ALU issue slots a launch used: its recorded
+    VALU wave instructions x 4 cycles (a 64-lane instruction on a 16-lane
+    SIMD) over 1024 SIMDs x 2.4 GHz x the launch time measured here."""
+    if not rec or "valu_insts_per_launch" not in rec:
+        return None
+    return round(rec["valu_insts_per_launch"] * 4 / (1024 * 2.4e9 * launch_ms * 1e-3), 4)
 
 
 def host_cpu():
@@ -537,8 +550,15 @@ def main():
             roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_PUBLISHED_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
         kname = "fd_fused_step_kernel" if fused else "fd_stage_kernel"
+        shape = ({"segment_rows": fd.fd_fused()} if fused else
+                 {"tile_rows": [tuned["fd_tile_rows"], tuned["fd_tile_rows_later_stages"]]})
+        rec = kernel_record(kname, n, shape)
         line["roofline"] = dict(
-            kernel=kname, **roof, traffic=kernel_traffic(kname, n),
+            kernel=kname, **roof, traffic=rec["bytes_per_launch"] if rec else None,
+            valu_issue_frac=valu_issue(rec, fd_stage_ms),
+            valu_issue="recorded SQ_INSTS_VALU per launch x 4 cycles / (1024 SIMDs x 2.4 GHz x the launch "
+                       "time measured here): the issue-slot share of the vector ALU (null when the record does "
+                       "not match this kernel's sources or launch shape)",
             bytes_per_launch=bytes_fd_stage, flops_per_launch=flops_launch,
             hbm_frac=round(hbm_frac, 4), alu_frac_published_peak=round(alu_frac, 4),
             alu_tflops=round(tflops, 2),
@@ -548,7 +568,10 @@ def main():
     else:
         line["roofline"] = {
             "kernel": "cs_step_vec_kernel", "bound": "hbm", "achieved": round(cs_gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(cs_gbs / HBM_PEAK_GBS, 4), "traffic": kernel_traffic("cs_step_vec_kernel", n)}
+            "unit": "GB/s", "frac": round(cs_gbs / HBM_PEAK_GBS, 4)}
+        rec = kernel_record("cs_step_vec_kernel", n)
+        line["roofline"]["traffic"] = rec["bytes_per_launch"] if rec else None
+        line["roofline"]["valu_issue_frac"] = valu_issue(rec, cs_ms)
     if args.copy_calibration:
         src = torch.empty(bytes_cs // 8, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -1,5 +1,6 @@
 """Host logic of bench.py (no GPU): the one-GPU contract and the reporting
-of measured kernel traffic only while the kernel's sources are unchanged."""
+of measured kernel traffic and VALU issue only while the kernel's sources and
+launch shape are those the counters were taken on."""
 import importlib.util
 import json
 import os
@@ -29,16 +30,22 @@ def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch
     csrc = os.path.join(ROOT, "paper_1904_02471_amd", "csrc")
     files = ["lb_fd_impl.h", "lb_fd.hip"]
     record = {"fd_stage_kernel": {"grid": [64, 64], "bytes_per_launch": 12345, "sources": files,
-                                  "sources_sha256": bench.source_digest(files)}}
+                                  "sources_sha256": bench.source_digest(files), "tile_rows": [8, 4],
+                                  "valu_insts_per_launch": 1.2e8}}
     pkg = tmp_path / "paper_1904_02471_amd"
     (pkg / "csrc").mkdir(parents=True)
     for f in files:
         (pkg / "csrc" / f).write_bytes(open(os.path.join(csrc, f), "rb").read())
     (pkg / "kernel_traffic.json").write_text(json.dumps(record))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.kernel_traffic("fd_stage_kernel", 64) == 12345
-    assert bench.kernel_traffic("fd_stage_kernel", 128) is None  # another workload
-    assert bench.kernel_traffic("cs_step_vec_kernel", 64) is None  # no record
+    rec = bench.kernel_record("fd_stage_kernel", 64, {"tile_rows": [8, 4]})
+    assert rec["bytes_per_launch"] == 12345
+    # 1.2e8 wave instructions x 4 cycles over 1024 SIMDs x 2.4 GHz x 0.25 ms
+    assert bench.valu_issue(rec, 0.25) == round(1.2e8 * 4 / (1024 * 2.4e9 * 0.25e-3), 4)
+    assert bench.valu_issue(None, 0.25) is None
+    assert bench.kernel_record("fd_stage_kernel", 64, {"tile_rows": [4, 4]}) is None  # another launch shape
+    assert bench.kernel_record("fd_stage_kernel", 128) is None  # another workload
+    assert bench.kernel_record("cs_step_vec_kernel", 64) is None  # no record
     with open(pkg / "csrc" / "lb_fd.hip", "ab") as fh:  # the kernel changed since the counters
         fh.write(b"\n// edited\n")
-    assert bench.kernel_traffic("fd_stage_kernel", 64) is None
+    assert bench.kernel_record("fd_stage_kernel", 64) is None
