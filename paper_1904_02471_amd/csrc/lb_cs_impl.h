@@ -401,7 +401,7 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
             row(un, rn_);
         }
         Chunk<T> out[9];
-        float held[9];  // FP16: the even node's values awaiting their pair
+        half2_bits held[9];  // FP16: the even node's values awaiting their pair
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             CT g[9], o[9];
@@ -436,12 +436,11 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 if constexpr (std::is_same<T, __half>::value) {
-                    // FP16: converted in pairs of nodes, one packed conversion each
-                    const float v = sr16_pre(o[k], rnd.next());
+                    // FP16: nodes in pairs, into the two halves of one word
                     if (j & 1)
-                        out[k].w[j >> 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(held[k], v));
+                        out[k].w[j >> 1] = __builtin_bit_cast(uint32_t, sr16_into(held[k], o[k], rnd.next(), true));
                     else
-                        held[k] = v;
+                        held[k] = sr16_into(half2_bits{}, o[k], rnd.next(), false);
                 } else {
                     out[k].set(j, o[k]);
                 }

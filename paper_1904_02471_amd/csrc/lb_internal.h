@@ -66,6 +66,12 @@ struct Params {
 // stored departures are small, and so is their FP16 rounding.  Always FP32
 // (c = {w0, w1, w5, a1, a5, b1, b5, rho0}), in every kernel that reads or
 // writes the storage, so that each path adds and removes the same value.
+// The constants are the collision's FP32 equilibrium constants and the
+// operations follow its equilibrium: evaluated otherwise (from terms shared
+// by the nine populations and the exact rational weights, equal to 1e-10),
+// the stored departures carried a rounding pattern correlated with the
+// flow, and the fitted viscosity of the 4096^2 vortex moved from +1e-4 ..
+// +2.5e-4 to +1.3e-3 on every seed.
 __host__ __device__ __forceinline__ float cs_ref_pop(int k, float ux, float uy, const float (&c)[8])
 {
     float eu, w, a, b;
@@ -113,39 +119,46 @@ __device__ __forceinline__ void store_from(double *p, double v) { *p = v; }
 __device__ __forceinline__ void store_from(float *p, double v) { *p = (float)v; }
 __device__ __forceinline__ void store_from(__half *p, double v) { *p = __builtin_bit_cast(__half, (_Float16)v); }
 
-// Stochastic rounding of an FP32 value to FP16 with 13 random bits r13
-// (0..8191).  sr16_pre returns an FP32 value whose conversion toward zero to
-// FP16 is the rounded value: v moves away from zero by r13 units of 2^-13 of
-// the FP16 step at v (2^-10 of its power of two in the FP16 normal range,
-// 2^-24 below 2^-14); in the FP16 normal range that is a whole number of
-// FP32 ulps of v, so the sum is exact.  The value then passes the upper FP16
-// neighbour with probability equal to its position between the two
-// neighbours, and the truncation keeps the lower one otherwise: exactly
+// Stochastic rounding of an FP32 value v to FP16 with 13 random bits r13
+// (0..8191): v moves away from zero by r13 units of 2^-13 of the FP16 step
+// at v (2^-10 of its power of two in the FP16 normal range, 2^-24 below
+// 2^-14), and the result is truncated toward zero to FP16.  The value thus
+// passes the upper FP16 neighbour with probability equal to its position
+// between the two neighbours, and keeps the lower one otherwise: exactly
 // unbiased in the FP16 normal range.  Below 2^-14 the FP32 bits of v finer
 // than 2^-37 are not randomised, which biases the result toward zero by less
 // than 2^-13 of an FP16 step (2^-37 absolute); below 2^-24 the choice is
 // between 0 and 2^-24.  A state that changes by less than an FP16 step per
 // time step thus still evolves correctly on average, where round-to-nearest
-// would hold it fixed.  No branches: every lane takes the same instructions
-// whatever the range of its value.
-__device__ __forceinline__ float sr16_pre(float v, uint32_t r13)
+// would hold it fixed.  gfx950's stochastic-rounding conversion
+// (v_cvt_sr_f16_f32) with r13 in bits 31..19 of its random operand does
+// exactly this, one instruction per value: it gave the same FP16 bits as the
+// arithmetic form (an exact fma of r13 and the 2^-13 step into v, then the
+// round-toward-zero conversion) on 2^20 values of both signs across the
+// normal, subnormal and below-2^-24 FP16 ranges.  Beyond the FP16 range it
+// gives +-inf where that form saturated at +-65504.
+typedef __fp16 half2_bits __attribute__((ext_vector_type(2)));
+
+// v rounded into the low (hi = false) or high half of the packed pair h.
+__device__ __forceinline__ half2_bits sr16_into(half2_bits h, float v, uint32_t r13, bool hi)
 {
-    const uint32_t b = __float_as_uint(v);
-    // 2^-13 of the FP16 step at v: exponent max(e, 113) - 23, the sign of v
-    const uint32_t e = max(b & 0x7f800000u, 113u << 23) - (23u << 23);
-    return __builtin_fmaf((float)r13, __uint_as_float((b & 0x80000000u) | e), v);
+    return hi ? __builtin_amdgcn_cvt_sr_f16_f32(h, v, r13 << 19, true)
+              : __builtin_amdgcn_cvt_sr_f16_f32(h, v, r13 << 19, false);
 }
 
 // Two stochastically rounded values as one packed FP16 pair (a in the low half).
 __device__ __forceinline__ uint32_t half2_sr_bits(float a, uint32_t ra13, float b, uint32_t rb13)
 {
-    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(sr16_pre(a, ra13), sr16_pre(b, rb13)));
+    half2_bits h = {};
+    h = sr16_into(h, a, ra13, false);
+    h = sr16_into(h, b, rb13, true);
+    return __builtin_bit_cast(uint32_t, h);
 }
 
 __device__ __forceinline__ __half half_sr(float v, uint32_t r13)
 {
-    const uint32_t w = half2_sr_bits(v, r13, 0.0f, 0u);
-    return __builtin_bit_cast(__half, (unsigned short)(w & 0xffffu));
+    const half2_bits h = sr16_into(half2_bits{}, v, r13, false);
+    return __builtin_bit_cast(__half, (unsigned short)(__builtin_bit_cast(uint32_t, h) & 0xffffu));
 }
 
 // Counter-based random bits (a 32-bit integer mixer) for (key, salt).
