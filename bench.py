@@ -569,7 +569,7 @@ def main():
         line["roofline"] = {
             "kernel": "cs_step_vec_kernel", "bound": "hbm", "achieved": round(cs_gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(cs_gbs / HBM_PEAK_GBS, 4)}
-        rec = kernel_record("cs_step_vec_kernel", n)
+        rec = kernel_record("cs_step_vec_kernel", n, {"threads": tuned["cs_threads"]})
         line["roofline"]["traffic"] = rec["bytes_per_launch"] if rec else None
         line["roofline"]["valu_issue_frac"] = valu_issue(rec, cs_ms)
     if args.copy_calibration:

@@ -15,7 +15,9 @@ Tolerances (per element of the canonical state f, absolute):
       tol = 32 u32 (n + 1) max|g| + 1e-13 (n + 1) max|f|.
   FP16 storage: the stored g carries a relative rounding of u16 = 2^-11 per
       step: tol = 2 u16 (n + 1) max|g| + the FP32 bound (FP16 relative to a
-      reference equilibrium stores smaller departures: the same bound).
+      reference equilibrium stores smaller departures: the same bound).  The
+      rounding is stochastic and unbiased, so the parity tests also hold the
+      rms error over the state to 2 u16 sqrt(n + 1) rms g.
 """
 import numpy as np
 

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1904_02471_amd import lb, workloads
-from tests.gpu_helpers import PREC_NAME, assert_state_close, field_errors, pair, tolerance
+from tests.gpu_helpers import PREC_NAME, U16, assert_state_close, field_errors, pair, tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +41,19 @@ def run_and_compare(g, o, steps, prec, what, fields=False):
         done = n
         fo = o.get_state()
         fg = g.get_state()
-        tol = tolerance(prec, n, fo, g.w, fo.sum(0).mean())
+        rho0 = fo.sum(0).mean()
+        tol = tolerance(prec, n, fo, g.w, rho0)
         assert_state_close(fg, fo, tol, "%s after %d steps" % (what, n))
+        if prec in (lb.LB_FP16_SHIFTED, lb.LB_FP16_REF):
+            # stochastic rounding: unbiased errors of at most one FP16 step
+            # (2 u16 |g|) per rounding, variance at most a quarter step squared;
+            # over the initial and n stepped roundings without amplification
+            # the rms error is at most u16 sqrt(n+1) rms g.  Asserted with a
+            # factor 2 (measured: 0.15-0.83 over these cases)
+            go = fo - g.w[:, None, None] * rho0
+            ratio = np.sqrt(np.mean((fg - fo) ** 2)) / (U16 * np.sqrt(n + 1) * np.sqrt(np.mean(go ** 2)))
+            print("%s after %d steps: rms error / (u16 sqrt(n+1) rms g) = %.3f" % (what, n, ratio), flush=True)
+            assert ratio <= 2.0, (what, n, ratio)
         if fields:
             e_rho, e_u = field_errors(g, o)
             print("%s after %d steps: rel-L2 rho-rho0 %.2e u %.2e" % (what, n, e_rho, e_u), flush=True)
