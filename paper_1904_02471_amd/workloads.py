@@ -88,6 +88,31 @@ def random_state(Nx, Ny, seed, cs, rho_range=(0.9, 1.1), u_max=0.05):
     return rho, ux, uy
 
 
+def separable_random_state(Nx, Ny, seed, u_max=0.02, rho_spread=0.01):
+    """A state that varies from node to node in both directions yet costs
+    one full-size array per field (for grids of ~1e9 nodes):
+    rho = 1 + rho_spread (a[i] + b[j]) / 2, u_x = u_max c[i] d[j],
+    u_y = u_max e[i] f[j], the 1-D factors uniform in [-1, 1] (seeded).
+    Returns rho, ux, uy and a function giving the three fields on the index
+    window (ys, xs) without slicing the full arrays."""
+    rng = np.random.default_rng(seed)
+    a, c, e = (rng.uniform(-1.0, 1.0, Nx) for _ in range(3))
+    b, d, f = (rng.uniform(-1.0, 1.0, Ny) for _ in range(3))
+
+    def window(ys, xs):
+        return (1.0 + 0.5 * rho_spread * np.add.outer(b[ys], a[xs]),
+                u_max * np.multiply.outer(d[ys], c[xs]), u_max * np.multiply.outer(f[ys], e[xs]))
+
+    rho = np.add.outer(b, a)
+    rho *= 0.5 * rho_spread
+    rho += 1.0
+    ux = np.multiply.outer(d, c)
+    ux *= u_max
+    uy = np.multiply.outer(f, e)
+    uy *= u_max
+    return rho, ux, uy, window
+
+
 def random_distribution(K, Nx, Ny, seed, weights, spread=0.2):
     """A non-equilibrium distribution: w_k (1 + spread * U[-1, 1])."""
     rng = np.random.default_rng(seed)
