@@ -146,15 +146,6 @@ __device__ __forceinline__ half2_bits sr16_into(half2_bits h, float v, uint32_t 
               : __builtin_amdgcn_cvt_sr_f16_f32(h, v, r13 << 19, false);
 }
 
-// Two stochastically rounded values as one packed FP16 pair (a in the low half).
-__device__ __forceinline__ uint32_t half2_sr_bits(float a, uint32_t ra13, float b, uint32_t rb13)
-{
-    half2_bits h = {};
-    h = sr16_into(h, a, ra13, false);
-    h = sr16_into(h, b, rb13, true);
-    return __builtin_bit_cast(uint32_t, h);
-}
-
 __device__ __forceinline__ __half half_sr(float v, uint32_t r13)
 {
     const half2_bits h = sr16_into(half2_bits{}, v, r13, false);
