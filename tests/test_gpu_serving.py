@@ -195,3 +195,48 @@ def test_apparent_viscosity_of_results():
         # and close to the viscosity the request was set up with
         nu0 = (e["tau_std"] - 0.5) / 3.0 if e["model"] == "cs" else kw["tau"]
         assert nu == pytest.approx(nu0, rel=0.05)
+
+
+def unstable_cs_request(n=32, seed=5):
+    """A CS request that blows up: tau = 0.5002 (omega near 2) and a random
+    state at up to 0.45 of the lattice speed; the FP64 oracle's populations
+    reach 1e12 after 25 steps and 1e28 after 50, so FP32 overflows within
+    ~60 steps and the diagnostics turn non-finite."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 1.5, (n, n))
+    ux, uy = rng.uniform(-0.45, 0.45, (2, n, n))
+    return dict(model=lb.LB_CS_D2Q9, Nx=n, Ny=n, tau=0.5002, dt=1.0, ds=1.0, N=2, rho=rho, ux=ux, uy=uy,
+                nsteps=200)
+
+
+def test_a_diverging_request_fails_alone():
+    """A request whose state overflows is reported with LB_ENAN and no
+    samples; the requests beside it in the batch, and one submitted after it,
+    give their single-simulation results bit for bit.  (Non-finite values are
+    ordinary arithmetic here: no kernel indexes by a state value.)"""
+    print("case: serving diverging request", flush=True)
+    good = [{"kind": "tgv", "side": 64, "model": "cs", "tau_std": 0.7, "steps": 120},
+            {"kind": "shear", "side": 64, "model": "fd16", "tau_std": 0.8, "steps": 60}]
+    fields = serve.field_cache()
+    srv = serve.Server(8 << 30, 64, 16)
+    srv.submit(sample_every=EVERY, tag=0, **serve.trace_request(good[0], fields))
+    srv.submit(sample_every=EVERY, tag=9, **unstable_cs_request())
+    srv.submit(sample_every=EVERY, tag=1, **serve.trace_request(good[1], fields))
+    res = {r["tag"]: r for r in serve.wait_all(srv, 3, 120)}
+    later = {"kind": "tgv", "side": 96, "model": "cs", "tau_std": 0.9, "steps": 40}
+    srv.submit(sample_every=EVERY, tag=2, **serve.trace_request(later, fields))
+    res.update({r["tag"]: r for r in serve.wait_all(srv, 1, 120)})
+    srv.close()
+    assert res[9]["status"] == lb.LB_ENAN and res[9]["samples"].shape[0] == 0
+    assert math.isnan(res[9]["nu_app"])
+    for tag, e in ((0, good[0]), (1, good[1]), (2, later)):
+        assert res[tag]["status"] == 0
+        assert np.array_equal(res[tag]["samples"], single_run(e)), e
+    # the single-simulation path reports the same condition
+    kw = unstable_cs_request()
+    g = lb.Sim(kw["model"], kw["Nx"], kw["Ny"], kw["tau"], kw["dt"], kw["ds"], kw["N"])
+    g.init(kw["rho"], kw["ux"], kw["uy"])
+    g.step(kw["nsteps"])
+    with pytest.raises(lb.LBError) as err:
+        g.reduce()
+    assert err.value.code == lb.LB_ENAN
