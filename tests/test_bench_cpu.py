@@ -31,7 +31,7 @@ def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch
     files = ["lb_fd_impl.h", "lb_fd.hip"]
     record = {"fd_stage_kernel": {"grid": [64, 64], "bytes_per_launch": 12345, "sources": files,
                                   "sources_sha256": bench.source_digest(files), "tile_rows": [8, 4],
-                                  "valu_insts_per_launch": 1.2e8}}
+                                  "valu_insts_per_launch": 1.2e8, "valu_pairs_per_launch": 3.0e7}}
     pkg = tmp_path / "paper_1904_02471_amd"
     (pkg / "csrc").mkdir(parents=True)
     for f in files:
@@ -40,8 +40,15 @@ def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     rec = bench.kernel_record("fd_stage_kernel", 64, {"tile_rows": [8, 4]})
     assert rec["bytes_per_launch"] == 12345
-    # 1.2e8 wave instructions x 4 cycles over 1024 SIMDs x 2.4 GHz x 0.25 ms
-    assert bench.valu_issue(rec, 0.25) == round(1.2e8 * 4 / (1024 * 2.4e9 * 0.25e-3), 4)
+    # 1.2e8 wave instructions, 3e7 of the quad-cycles issuing two, over the
+    # 1024 SIMDs x 0.6e9 quad-cycles per second x 0.25 ms
+    quads = 1024 * 0.6e9 * 0.25e-3
+    issue = bench.valu_issue(rec, 0.25)
+    assert issue["insts_per_quad_cycle"] == round(1.2e8 / quads, 4)
+    assert issue["busy_frac"] == round((1.2e8 - 3.0e7) / quads, 4)
+    assert issue["paired_share"] == 0.5
+    del rec["valu_pairs_per_launch"]
+    assert set(bench.valu_issue(rec, 0.25)) == {"insts_per_quad_cycle"}
     assert bench.valu_issue(None, 0.25) is None
     assert bench.kernel_record("fd_stage_kernel", 64, {"tile_rows": [4, 4]}) is None  # another launch shape
     assert bench.kernel_record("fd_stage_kernel", 128) is None  # another workload
