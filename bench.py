@@ -127,6 +127,41 @@ def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
     return out
 
 
+def host_boundary(lb, workloads, units, sims, n, K):
+    """Cost of the C ABI's host buffers around a K-step job on the n x n
+    workload: lb_init from host rho, u (3 FP64 fields, 24 B per node up,
+    plus the equilibrium initialisation) and lb_moments back to host (24 B
+    per node down, plus the moments kernel), wall clock with the device
+    idle before each call, second of two calls.  `pcie_inclusive_mlups` is
+    the job's rate with both transfers counted: nodes x K / (t_init + K x
+    t_step + t_moments); it is never the headline value (whose inputs are
+    resident in HBM).  Re-initialises the simulations (after the timed
+    steps)."""
+    import torch
+    out = {}
+    nodes = n * n
+    fields = {"cs_d2q9": workloads.taylor_green(n, n, 0.01, 1.0 / 3.0)[:3],
+              "fd_d2q16": workloads.taylor_green(n, n, units.velocity_fd_from_std(0.01), 1.0)[:3]}
+    for name, sim, step_ms in sims:
+        r, ux, uy = fields[name]
+        t_init = t_mom = 0.0
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.init(r, ux, uy)
+            sim.synchronize()
+            t1 = time.perf_counter()
+            sim.moments()
+            t2 = time.perf_counter()
+            t_init, t_mom = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+        job_ms = t_init + K * step_ms + t_mom
+        out[name] = {"init_ms": round(t_init, 3), "moments_ms": round(t_mom, 3),
+                     "bytes_up": 24 * nodes, "bytes_down": 24 * nodes,
+                     "steps": K, "pcie_inclusive_mlups": round(nodes * K / (job_ms * 1e-3) / 1e6, 1),
+                     "resident_mlups": round(nodes / (step_ms * 1e-3) / 1e6, 1)}
+    return out
+
+
 def fd_d2q36(lb, workloads, units, stream, n=2048, steps=20, warmup=3):
     """FD D2Q36 (N = 4) plain steps on the n x n Taylor-Green vortex of the
     D2Q36 workload (tau_FD = 5e-4, dt at CFL 0.5), FP32 storage, autotuned."""
@@ -592,6 +627,9 @@ def main():
         ms = a.elapsed_time(b) / 20
         line["copy_calibration"] = {"bytes_moved": 2 * src.numel() * 4, "ms": round(ms, 5),
                                     "gbs": round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
+    line["host_boundary"] = host_boundary(
+        lb, workloads, units, [(nm, sim, ms) for nm, sim, ms, on in
+                               (("cs_d2q9", cs, cs_ms, run_cs), ("fd_d2q16", fd, fd_ms, run_fd)) if on], n, K)
     if args.only is None and not args.no_cache_free:
         cs.destroy()
         fd.destroy()
