@@ -262,8 +262,18 @@ int lb_set_rounding_seed(lb_sim *sim, unsigned seed);
  * hold more registers and LDS), then, where lb_set_fd_fused applies, the
  * three stage launches against the fused step with 32-, 64- and 128-row
  * segments.  Synchronises the stream.  LB_ESTATE before
- * lb_init, LB_EINVAL for reps outside [1, 1000]. */
+ * lb_init, LB_EINVAL for reps outside [1, 1000].  The choice is kept in a
+ * process-wide cache keyed by device, model, storage, boundaries, grid and
+ * Hermite order; a later call for a handle of the same key (any handle, any
+ * thread) takes the cached shapes without timing. */
 int lb_autotune(lb_sim *sim, int reps);
+
+/* Empty the autotuning cache, so that the next lb_autotune of each key times
+ * its candidates again.  Returns LB_OK. */
+int lb_tuning_cache_clear(void);
+
+/* Number of keys in the autotuning cache. */
+int lb_tuning_cache_size(void);
 
 /* Set the plain-step launch shapes directly: cs_threads 0 (one chunk per
  * thread) or a multiple of 64 up to 1024; fd_rows (first FD stage) and

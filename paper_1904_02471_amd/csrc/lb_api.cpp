@@ -7,7 +7,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -844,11 +847,66 @@ int lb_step(lb_sim *s, int nsteps)
     return LB_OK;
 }
 
+namespace {
+
+// Launch shapes chosen by lb_autotune, per device and simulation shape (the
+// timings depend on the kernels and the grid, not on tau, dt or the state),
+// shared by every handle of the process.
+struct TuneKey {
+    int device, model, prec, fixed, imex, Nx, Ny, N;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(device, model, prec, fixed, imex, Nx, Ny, N) <
+               std::tie(o.device, o.model, o.prec, o.fixed, o.imex, o.Nx, o.Ny, o.N);
+    }
+};
+struct TuneVal {
+    int cs_threads, fd_rows, fd_rows_rest, fd_fused_ys;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
+TuneKey tune_key(const lb_sim *s)
+{
+    return {s->device, s->model, (int)s->prec, s->fixed ? 1 : 0, s->imex ? 1 : 0, s->Nx, s->Ny, s->N};
+}
+
+}  // namespace
+
+int lb_tuning_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+    return LB_OK;
+}
+
+int lb_tuning_cache_size(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int)g_tune_cache.size();
+}
+
 int lb_autotune(lb_sim *s, int reps)
 {
     if (!s || reps < 1 || reps > 1000) return fail(LB_EINVAL);
     if (!s->ready) return fail(LB_ESTATE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    const TuneKey key = tune_key(s);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const TuneVal &v = it->second;
+            if (v.cs_threads != s->cs_threads || v.fd_rows != s->fd_rows || v.fd_rows_rest != s->fd_rows_rest ||
+                v.fd_fused_ys != s->fd_fused_ys)
+                drop_graphs(s);
+            s->cs_threads = v.cs_threads;
+            s->fd_rows = v.fd_rows;
+            s->fd_rows_rest = v.fd_rows_rest;
+            s->fd_fused_ys = v.fd_fused_ys;
+            return LB_OK;
+        }
+    }
     // the fastest of the candidates of one choice (cs_threads or the tile
     // rows of one FD stage); the first candidate when there is no choice
     auto pick = [&](const std::vector<int> &cand, int fd_stage, int *out) -> hipError_t {
@@ -902,6 +960,8 @@ int lb_autotune(lb_sim *s, int reps)
     s->fd_rows = rows1;
     s->fd_rows_rest = rows_rest;
     s->fd_fused_ys = fused;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {cs_threads, rows1, rows_rest, fused};
     return LB_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_
            "lb_run_sampled",
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
            "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_rounding_seed", "lb_autotune", "lb_set_tuning",
-           "lb_set_fd_fused", "lb_get_fd_fused",
+           "lb_set_fd_fused", "lb_get_fd_fused", "lb_tuning_cache_clear", "lb_tuning_cache_size",
            "lb_get_tuning", "lb_set_stream", "lb_synchronize",
            "lb_device_bytes",
            "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
@@ -71,6 +71,8 @@ def _load():
         "lb_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lb_set_rounding_seed": (ctypes.c_int, [_vp, ctypes.c_uint]),
         "lb_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_tuning_cache_clear": (ctypes.c_int, []),
+        "lb_tuning_cache_size": (ctypes.c_int, []),
         "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "lb_set_fd_fused": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lb_get_fd_fused": (ctypes.c_int, [_vp]),
@@ -102,6 +104,16 @@ def _check(rc, what):
     if rc != LB_OK:
         raise LBError(rc, what)
     return rc
+
+
+def tuning_cache_clear():
+    """Empty the library's autotuning cache (lb_tuning_cache_clear)."""
+    _check(_lib.lb_tuning_cache_clear(), "lb_tuning_cache_clear")
+
+
+def tuning_cache_size():
+    """Number of keys in the library's autotuning cache."""
+    return int(_lib.lb_tuning_cache_size())
 
 
 def strerror(code):

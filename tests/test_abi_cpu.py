@@ -85,6 +85,12 @@ def test_create_validation(args, code):
     assert lb.strerror(code) not in ("", "unknown status")
 
 
+def test_tuning_cache_host_calls():
+    # host-only entry points: no device needed
+    assert lb._lib.lb_tuning_cache_clear() == lb.LB_OK
+    assert lb.tuning_cache_size() == 0
+
+
 def test_null_handles_are_rejected():
     assert lb._lib.lb_step(None, 1) == lb.LB_EINVAL
     assert lb._lib.lb_reduce(None, None) == lb.LB_EINVAL

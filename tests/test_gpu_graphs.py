@@ -114,3 +114,35 @@ def test_launch_shapes_do_not_change_results(model, Nx, Ny, prec, shapes):
     g.step_sampled(23, 4)
     assert np.array_equal(g.get_state(), ref[0])
     assert np.array_equal(g.series_read(), ref[1])
+
+
+def test_autotune_cache():
+    """lb_autotune keeps its choice per device, model, storage, boundaries,
+    grid and order: a second handle of the same key takes the cached shapes
+    (whatever shapes it held) without a new entry, a new grid or model adds
+    one, and clearing the cache empties it."""
+    print("case: autotune cache", flush=True)
+    lb.tuning_cache_clear()
+    assert lb.tuning_cache_size() == 0
+    sims = []
+    for Nx, Ny in ((96, 80), (96, 80), (128, 80)):
+        g = make(lb.LB_FD_D2Q16, Nx, Ny, lb.LB_FP32)
+        rho, ux, uy = workloads.random_state(Nx, Ny, 5, 1.0)
+        g.init(rho, ux, uy)
+        sims.append(g)
+    first = sims[0].autotune(2), sims[0].fd_fused()
+    assert lb.tuning_cache_size() == 1
+    other = (0, 4, 8) if first[0] != (0, 4, 8) else (0, 8, 4)
+    sims[1].set_tuning(*other)
+    sims[1].set_fd_fused(0 if first[1] else 32)
+    assert (sims[1].autotune(2), sims[1].fd_fused()) == first
+    assert lb.tuning_cache_size() == 1
+    sims[2].autotune(2)
+    assert lb.tuning_cache_size() == 2
+    cs = make(lb.LB_CS_D2Q9, 96, 80, lb.LB_FP32)
+    rho, ux, uy = workloads.random_state(96, 80, 6, 3.0 ** -0.5)
+    cs.init(rho, ux, uy)
+    cs.autotune(2)
+    assert lb.tuning_cache_size() == 3
+    lb.tuning_cache_clear()
+    assert lb.tuning_cache_size() == 0
