@@ -68,6 +68,9 @@ def parse():
                          "R > 0 the temporally blocked step with R-row segments (profiling runs)")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving stream to replay (0: skip; 512: the whole stream)")
+    ap.add_argument("--serving-batched-only", action="store_true",
+                    help="replay the stream batched only, without the one-simulation-per-launch comparison "
+                         "(profiling runs)")
     return ap.parse_args()
 
 
@@ -360,7 +363,7 @@ def decay_fit_args(entry, kw):
     return 2 * k * k, (omega if omega * kw["nsteps"] * kw["dt"] >= 4 * math.pi else 0.0)
 
 
-def serving_bench(n_requests, every):
+def serving_bench(n_requests, every, batched_only=False):
     """Replay the first n_requests of the seeded serving stream (Poisson
     arrivals, mean gap 2 ms; square grids 64..1024; CS D2Q9 or FD D2Q16;
     500-5000 steps) twice on the GPU: batched (lb_server, continuous
@@ -402,6 +405,14 @@ def serving_bench(n_requests, every):
     lat_b = np.array([results[i]["t_finish"] - (c0 + trace[i]["arrival_s"]) for i in range(n)])
     svc_b = np.array([results[i]["t_finish"] - results[i]["t_admit"] for i in range(n)])
     assert all(results[i]["status"] == 0 for i in range(n))
+    batched = {"sims_per_s": round(n / wall_b, 3), "wall_s": round(wall_b, 3),
+               "p50_s": round(float(np.percentile(lat_b, 50)), 4), "p99_s": round(float(np.percentile(lat_b, 99)), 4),
+               "service_p50_s": round(float(np.percentile(svc_b, 50)), 4),
+               "service_p99_s": round(float(np.percentile(svc_b, 99)), 4),
+               "mlups": round(sum(kw["Nx"] * kw["Ny"] * kw["nsteps"] for kw in reqs) / wall_b / 1e6, 1),
+               "batch_steps": stats["batch_steps"]}
+    if batched_only:
+        return {"requests": n, "batched": batched}
 
     # one simulation per launch sequence
     lat_s = np.zeros(n)
@@ -443,10 +454,7 @@ def serving_bench(n_requests, every):
     return {
         "requests": n, "stream": "seed 1904, Poisson arrivals mean 2 ms, side U{64..1024}, CS D2Q9 / FD D2Q16 "
                                   "50/50, tau U[0.55,1.5], steps U{500..5000}, FP32, diagnostics every %d" % every,
-        "batched": {"sims_per_s": round(n / wall_b, 3), "wall_s": round(wall_b, 3),
-                    "p50_s": pct(lat_b, 50), "p99_s": pct(lat_b, 99),
-                    "service_p50_s": pct(svc_b, 50), "service_p99_s": pct(svc_b, 99),
-                    "mlups": round(nodes_steps / wall_b / 1e6, 1), "batch_steps": stats["batch_steps"]},
+        "batched": batched,
         "one_sim_per_launch": {"sims_per_s": round(n / wall_s, 3), "wall_s": round(wall_s, 3),
                                "p50_s": pct(lat_s, 50), "p99_s": pct(lat_s, 99),
                                "service_p50_s": pct(svc_s, 50), "service_p99_s": pct(svc_s, 99),
@@ -640,7 +648,7 @@ def main():
         if args.only is not None or args.no_cache_free:
             cs.destroy()
             fd.destroy()
-        line["serving"] = serving_bench(args.serving_requests, every)
+        line["serving"] = serving_bench(args.serving_requests, every, args.serving_batched_only)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(every, n)
     print(json.dumps(line), flush=True)
