@@ -112,6 +112,7 @@ def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
         sim.init(r, ux, uy)
         del r, ux, uy
         threads = sim.autotune(10)[0]
+        nt = sim.cs_nontemporal()
         sim.step(warmup)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -125,7 +126,7 @@ def cache_free_cs(lb, workloads, stream, n=4096, steps=200, warmup=20):
         gbs = bpn * n * n / (ms * 1e-3) / 1e9
         out[name] = {"ms_per_step": round(ms, 5), "mlups": round(n * n / (ms * 1e-3) / 1e6, 1),
                      "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "bytes_per_node_step": bpn, "cs_threads": threads}
+                     "bytes_per_node_step": bpn, "cs_threads": threads, "cs_nontemporal_stores": nt}
         sim.destroy()
     return out
 
@@ -497,6 +498,7 @@ def main():
         fd.set_fd_fused(args.fd_fused)
     tuned = {"cs_threads": cs.autotune(10)[0], "fd_tile_rows": fd_tuned[1], "fd_tile_rows_later_stages": fd_tuned[2],
              "fd_fused_segment_rows": fd.fd_fused()}
+    tuned["cs_nontemporal_stores"] = cs.cs_nontemporal()
     fused = fd.fd_fused() > 0
     run_cs = args.only in (None, "cs")
     run_fd = args.only in (None, "fd")
@@ -619,7 +621,10 @@ def main():
         line["roofline"] = {
             "kernel": "cs_step_vec_kernel", "bound": "hbm", "achieved": round(cs_gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(cs_gbs / HBM_PEAK_GBS, 4)}
-        rec = kernel_record("cs_step_vec_kernel", n, {"threads": tuned["cs_threads"]})
+        # workgroup size 0 is one 4-value chunk per thread: the row's chunk
+        # count rounded up to whole waves, within [256, 1024]
+        threads = tuned["cs_threads"] or min(1024, max(256, -(-(n // 4) // 64) * 64))
+        rec = kernel_record("cs_step_vec_kernel", n, {"threads": threads, "nt": tuned["cs_nontemporal_stores"]})
         line["roofline"]["traffic"] = rec["bytes_per_launch"] if rec else None
         line["roofline"]["valu_issue"] = valu_issue(rec, cs_ms)
     if args.copy_calibration:

@@ -256,7 +256,8 @@ int lb_set_rounding_seed(lb_sim *sim, unsigned seed);
  * results are bitwise the same for every shape).  Times `reps` launches of
  * each candidate on the handle's own buffers, leaving the state unchanged,
  * and keeps the fastest: CS (vector row form only) workgroup sizes of 256,
- * 512 and 1024 threads against one chunk per thread; FD tiles of 64 x 32 and
+ * 512 and 1024 threads against one chunk per thread, then at that size
+ * plain against non-temporal stores (lb_set_cs_nontemporal); FD tiles of 64 x 32 and
  * 64 x 16 nodes, chosen separately for the first Runge-Kutta stage and for
  * the later stages (which also read the step's base state, so their kernels
  * hold more registers and LDS), then, where lb_set_fd_fused applies, the
@@ -300,6 +301,18 @@ int lb_get_fd_fused(const lb_sim *sim);
 
 /* The current plain-step launch shapes (host ints). */
 int lb_get_tuning(const lb_sim *sim, int *cs_threads, int *fd_rows, int *fd_rows_rest);
+
+/* Store policy of CS plain steps: 1 stores the vector row form's outputs
+ * non-temporally (the written lines are not kept in the caches; faster only
+ * for states well beyond the 256 MB last-level cache), 0 (the default of a
+ * new handle) plainly.  Results are bitwise the same; sampled steps and the
+ * scalar row form store plainly.  LB_EINVAL for an FD handle or a value
+ * other than 0 and 1. */
+int lb_set_cs_nontemporal(lb_sim *sim, int on);
+
+/* The CS store policy of plain steps: 1 non-temporal, 0 plain (LB_EINVAL
+ * for a NULL handle). */
+int lb_get_cs_nontemporal(const lb_sim *sim);
 
 /* Launch on a caller-owned HIP stream (hipStream_t passed as void*; NULL
  * means the library's own stream).  The caller keeps the stream alive. */

@@ -232,7 +232,8 @@ hipError_t step_once(lb_sim *s, bool with_diag)
     const DiagArgs<CT> *dp = with_diag ? &d : nullptr;
     hipError_t e = hipSuccess;
     if (s->cs) {
-        e = launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, dp, s->stream, s->cs_threads);
+        e = launch_cs_step_st<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, dp, s->stream, s->cs_threads,
+                                 s->cs_nt);
         s->cur ^= 1;
     } else {
         T *g = bufp<T>(s, 0), *a = bufp<T>(s, 1), *b = bufp<T>(s, 2);
@@ -336,15 +337,33 @@ hipError_t plain_steps(lb_sim *s, long long n)
 // handle's own buffers with launches that leave the state untouched: a CS
 // step from the current buffer into the other one (which the next step
 // overwrites), FD stage 1 into the stage buffer A or stage 2 from A into B.
-// fd_stage selects the FD stage timed (its tile rows fd_rows).
+// fd_stage selects the FD stage timed (its tile rows fd_rows); cs_nt the CS
+// store policy.  With `scratch` (a device buffer of the handle's buffer
+// size) the timed CS launches ping-pong between the other buffer and it, as
+// consecutive steps do, so that each launch reads what the previous one
+// wrote: whether that is still in the last-level cache is what the store
+// policy changes.
 template <typename T>
-hipError_t time_candidate(lb_sim *s, int cs_threads, int fd_stage, int fd_rows, int reps, float *ms)
+hipError_t time_candidate(lb_sim *s, int cs_threads, bool cs_nt, int fd_stage, int fd_rows, int reps, float *ms,
+                          void *scratch = nullptr)
 {
     using CT = typename Arith<T>::type;
     const Params<CT> p = make_params<CT>(s);
     T *g = s->cs ? nullptr : bufp<T>(s, 0), *a = s->cs ? nullptr : bufp<T>(s, 1), *b = s->cs ? nullptr : bufp<T>(s, 2);
+    int nlaunch = 0;
     auto launch = [&]() -> hipError_t {
-        if (s->cs) return launch_cs_step<T>(bufp<T>(s, s->cur), bufp<T>(s, 1 - s->cur), p, nullptr, s->stream, cs_threads);
+        if (s->cs) {
+            const T *src = bufp<T>(s, s->cur);
+            T *dst = bufp<T>(s, 1 - s->cur);
+            if (scratch && nlaunch > 0) {
+                // other -> scratch, scratch -> other, ...
+                T *x = bufp<T>(s, 1 - s->cur), *y = static_cast<T *>(scratch);
+                src = (nlaunch & 1) ? x : y;
+                dst = (nlaunch & 1) ? y : x;
+            }
+            ++nlaunch;
+            return launch_cs_step_st<T>(src, dst, p, nullptr, s->stream, cs_threads, cs_nt);
+        }
         if (fd_stage == 1) return launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, fd_rows);
         return launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, fd_rows);
     };
@@ -862,6 +881,7 @@ struct TuneKey {
 };
 struct TuneVal {
     int cs_threads, fd_rows, fd_rows_rest, fd_fused_ys;
+    bool cs_nt;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
@@ -898,14 +918,24 @@ int lb_autotune(lb_sim *s, int reps)
         if (it != g_tune_cache.end()) {
             const TuneVal &v = it->second;
             if (v.cs_threads != s->cs_threads || v.fd_rows != s->fd_rows || v.fd_rows_rest != s->fd_rows_rest ||
-                v.fd_fused_ys != s->fd_fused_ys)
+                v.fd_fused_ys != s->fd_fused_ys || v.cs_nt != s->cs_nt)
                 drop_graphs(s);
             s->cs_threads = v.cs_threads;
+            s->cs_nt = v.cs_nt;
             s->fd_rows = v.fd_rows;
             s->fd_rows_rest = v.fd_rows_rest;
             s->fd_fused_ys = v.fd_fused_ys;
             return LB_OK;
         }
+    }
+    // CS vector rows: a scratch buffer for timing consecutive steps (without
+    // it, the workgroup sizes are timed from the current buffer and the
+    // stores stay plain)
+    const bool cs_vec = s->cs && !s->fixed && s->Nx % (s->prec == P64 ? 2 : 4) == 0;
+    void *scratch = nullptr;
+    if (cs_vec && hipMalloc(&scratch, s->buf_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        scratch = nullptr;
     }
     // the fastest of the candidates of one choice (cs_threads or the tile
     // rows of one FD stage); the first candidate when there is no choice
@@ -916,8 +946,8 @@ int lb_autotune(lb_sim *s, int reps)
             float ms = 0.0f;
             hipError_t e = with_type(s, [&](auto *tag) {
                 using T = std::remove_pointer_t<decltype(tag)>;
-                return s->cs ? time_candidate<T>(s, cand[i], 0, 8, reps, &ms)
-                             : time_candidate<T>(s, 0, fd_stage, cand[i], reps, &ms);
+                return s->cs ? time_candidate<T>(s, cand[i], false, 0, 8, reps, &ms, scratch)
+                             : time_candidate<T>(s, 0, false, fd_stage, cand[i], reps, &ms);
             });
             if (e != hipSuccess) return e;
             if (i == 0 || ms < best) {
@@ -928,10 +958,24 @@ int lb_autotune(lb_sim *s, int reps)
         return hipSuccess;
     };
     int cs_threads = s->cs_threads, rows1 = s->fd_rows, rows_rest = s->fd_rows_rest;
+    bool cs_nt = false;
     hipError_t e = hipSuccess;
     if (s->cs) {
-        const int w = s->prec == P64 ? 2 : 4;  // values per vector chunk
-        if (!s->fixed && s->Nx % w == 0) e = pick({0, 256, 512, 1024}, 0, &cs_threads);
+        if (cs_vec) {
+            e = pick({0, 256, 512, 1024}, 0, &cs_threads);
+            // then the store policy at that workgroup size: non-temporal
+            // stores pay only when the state is far larger than the
+            // last-level cache, which the timing finds out
+            float t_plain = 0.0f, t_nt = 0.0f;
+            if (e == hipSuccess && scratch)
+                e = with_type(s, [&](auto *tag) {
+                    using T = std::remove_pointer_t<decltype(tag)>;
+                    hipError_t r = time_candidate<T>(s, cs_threads, false, 0, 8, reps, &t_plain, scratch);
+                    if (r == hipSuccess) r = time_candidate<T>(s, cs_threads, true, 0, 8, reps, &t_nt, scratch);
+                    return r;
+                });
+            if (e == hipSuccess && scratch) cs_nt = t_nt < t_plain;
+        }
     } else {
         e = pick({8, 4}, 1, &rows1);
         if (e == hipSuccess) e = pick({8, 4}, 2, &rows_rest);
@@ -942,8 +986,8 @@ int lb_autotune(lb_sim *s, int reps)
     int fused = 0;
     if (e == hipSuccess && !s->cs && !s->imex && s->prec == P32 && fd_fused_supported(s->Q, s->fixed)) {
         float t1 = 0.0f, t2 = 0.0f;
-        e = time_candidate<float>(s, 0, 1, rows1, reps, &t1);
-        if (e == hipSuccess) e = time_candidate<float>(s, 0, 2, rows_rest, reps, &t2);
+        e = time_candidate<float>(s, 0, false, 1, rows1, reps, &t1);
+        if (e == hipSuccess) e = time_candidate<float>(s, 0, false, 2, rows_rest, reps, &t2);
         float best = t1 + 2.0f * t2;
         for (int ys : {32, 64, 128}) {
             float tf = 0.0f;
@@ -954,15 +998,35 @@ int lb_autotune(lb_sim *s, int reps)
             }
         }
     }
+    if (scratch) {
+        // the timed launches are complete (each timing waits for its end event)
+        if (hipFree(scratch) != hipSuccess && e == hipSuccess) e = hipErrorUnknown;
+    }
     if (e != hipSuccess) return fail(dev_status(e));
     drop_graphs(s);
     s->cs_threads = cs_threads;
+    s->cs_nt = cs_nt;
     s->fd_rows = rows1;
     s->fd_rows_rest = rows_rest;
     s->fd_fused_ys = fused;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {cs_threads, rows1, rows_rest, fused};
+    g_tune_cache[key] = {cs_threads, rows1, rows_rest, fused, cs_nt};
     return LB_OK;
+}
+
+int lb_set_cs_nontemporal(lb_sim *s, int on)
+{
+    if (!s || (on != 0 && on != 1) || !s->cs) return fail(LB_EINVAL);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    if (s->cs_nt != (on != 0)) drop_graphs(s);
+    s->cs_nt = on != 0;
+    return LB_OK;
+}
+
+int lb_get_cs_nontemporal(const lb_sim *s)
+{
+    if (!s) return fail(LB_EINVAL);
+    return s->cs_nt ? 1 : 0;
 }
 
 int lb_set_tuning(lb_sim *s, int cs_threads, int fd_rows, int fd_rows_rest)

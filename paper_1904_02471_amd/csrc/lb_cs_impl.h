@@ -184,6 +184,17 @@ struct Chunk {
         else
             *reinterpret_cast<uint2 *>(p) = make_uint2(w[0], w[1]);
     }
+    // the same store, marked non-temporal (the written lines are not kept
+    // in the caches for reuse)
+    __device__ __forceinline__ void store_nt(T *p) const
+    {
+        typedef uint32_t V4 __attribute__((ext_vector_type(4)));
+        typedef uint32_t V2 __attribute__((ext_vector_type(2)));
+        if constexpr (NW == 4)
+            __builtin_nontemporal_store(V4{w[0], w[1], w[2], w[3]}, reinterpret_cast<V4 *>(p));
+        else
+            __builtin_nontemporal_store(V2{w[0], w[1]}, reinterpret_cast<V2 *>(p));
+    }
     __device__ __forceinline__ T get(int j) const
     {
         T v;
@@ -311,8 +322,10 @@ __device__ __forceinline__ void cs_row(const T *__restrict__ src, T *__restrict_
 // them), collides its W nodes with cs_collide and stores whole chunks: the
 // same values as cs_row, with full-width memory accesses.  Any workgroup
 // size that is a multiple of 64 (up to 1024) works; with one chunk per
-// thread all loads of a row are in flight at once.
-template <typename T, bool DIAG, bool REF = false>
+// thread all loads of a row are in flight at once.  NT: the output chunks
+// are stored non-temporally (for states far larger than the last-level
+// cache, where the next step's reads cannot hit the written lines anyway).
+template <typename T, bool DIAG, bool REF = false, bool NT = false>
 __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restrict__ dst,
                                            const Params<typename Arith<T>::type> &p,
                                            const DiagArgs<typename Arith<T>::type> &d, int y, int diag_block)
@@ -448,7 +461,12 @@ __device__ __forceinline__ void cs_row_vec(const T *__restrict__ src, T *__restr
             if (DIAG) cs_diag_node_q(acc, m, d.ax != nullptr, qx[j], qy[j]);
         }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) out[k].store(orow + k * P + x);
+        for (int k = 0; k < 9; ++k) {
+            if constexpr (NT)
+                out[k].store_nt(orow + k * P + x);
+            else
+                out[k].store(orow + k * P + x);
+        }
     }
     if (DIAG) block_diag_store(acc, d.partial, diag_block);
 }

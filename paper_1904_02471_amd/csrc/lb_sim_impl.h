@@ -60,6 +60,7 @@ struct lb_sim {
     // of the later ones (which also read the step's base state).  Results do
     // not depend on them.
     int cs_threads = 0;
+    bool cs_nt = false;  // CS vector rows of plain steps: non-temporal stores
     int fd_rows = 8;
     int fd_rows_rest = 4;
     // FD plain steps by the temporally blocked kernel with y-segments of this
@@ -83,5 +84,11 @@ int diag_blocks_fused(const lb_sim *s);
 void finish_diag(const lb_sim *s, const double *raw, double vscale, double *out);
 // Decay rate of an amplitude series (lb_fit_decay): LB_OK or an LB_E* code.
 int fit_decay_rate(const double *t, const double *amp, int n, double omega, double *rate);
+// A CS step with a store policy: nt selects non-temporal stores for the
+// vector row form of plain steps (sampled steps and scalar rows store
+// plainly); launch_cs_step is this with nt = false.
+template <typename T>
+hipError_t launch_cs_step_st(const T *src, T *dst, const Params<typename Arith<T>::type> &p,
+                             const DiagArgs<typename Arith<T>::type> *diag, hipStream_t s, int threads, bool nt);
 
 }  // namespace lbm

@@ -26,6 +26,7 @@ EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_
            "lb_step_sampled", "lb_series_reserve", "lb_series_read",
            "lb_get_state", "lb_set_state", "lb_steps_done", "lb_set_graph_steps", "lb_set_rounding_seed", "lb_autotune", "lb_set_tuning",
            "lb_set_fd_fused", "lb_get_fd_fused", "lb_tuning_cache_clear", "lb_tuning_cache_size",
+           "lb_set_cs_nontemporal", "lb_get_cs_nontemporal",
            "lb_get_tuning", "lb_set_stream", "lb_synchronize",
            "lb_device_bytes",
            "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
@@ -72,6 +73,8 @@ def _load():
         "lb_set_rounding_seed": (ctypes.c_int, [_vp, ctypes.c_uint]),
         "lb_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
         "lb_tuning_cache_clear": (ctypes.c_int, []),
+        "lb_set_cs_nontemporal": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "lb_get_cs_nontemporal": (ctypes.c_int, [_vp]),
         "lb_tuning_cache_size": (ctypes.c_int, []),
         "lb_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "lb_set_fd_fused": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -274,6 +277,13 @@ class Sim:
 
     def fd_fused(self):
         return _lib.lb_get_fd_fused(self._h)
+
+    def set_cs_nontemporal(self, on):
+        """CS plain steps: non-temporal (True) or plain (False) stores."""
+        _check(_lib.lb_set_cs_nontemporal(self._h, 1 if on else 0), "lb_set_cs_nontemporal")
+
+    def cs_nontemporal(self):
+        return bool(_lib.lb_get_cs_nontemporal(self._h))
 
     def tuning(self):
         """(cs_threads, fd_rows, fd_rows_rest) of the plain steps."""

@@ -146,3 +146,30 @@ def test_autotune_cache():
     assert lb.tuning_cache_size() == 3
     lb.tuning_cache_clear()
     assert lb.tuning_cache_size() == 0
+
+
+@pytest.mark.parametrize("prec,Nx,Ny", [(lb.LB_FP32, 128, 40), (lb.LB_FP16_SHIFTED, 96, 24),
+                                        (lb.LB_FP16_REF, 64, 20), (lb.LB_FP64, 68, 12)])
+def test_cs_store_policy_does_not_change_results(prec, Nx, Ny):
+    """Non-temporal stores of the CS vector rows give bitwise the states and
+    diagnostics of plain stores, with graph replay and sampled steps mixed
+    in; the policy is rejected for FD handles."""
+    print("case: CS store policy", prec, Nx, Ny, flush=True)
+    out = []
+    for nt in (False, True):
+        g = make(lb.LB_CS_D2Q9, Nx, Ny, prec)
+        rho, ux, uy = workloads.random_state(Nx, Ny, 11, 3.0 ** -0.5)
+        g.init(rho, ux, uy)
+        g.set_probe(*workloads.separable_pattern("tgv", Nx, Ny))
+        g.series_reserve(16)
+        g.set_cs_nontemporal(nt)
+        assert g.cs_nontemporal() == nt
+        g.step(19)
+        g.step_sampled(21, 4)
+        g.step(3)
+        out.append((g.get_state(), g.series_read()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    fd = make(lb.LB_FD_D2Q16, 16, 16, lb.LB_FP32)
+    with pytest.raises(lb.LBError):
+        fd.set_cs_nontemporal(True)
