@@ -68,6 +68,9 @@ def parse():
                          "R > 0 the temporally blocked step with R-row segments (profiling runs)")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving stream to replay (0: skip; 512: the whole stream)")
+    ap.add_argument("--serving-node-limit", type=int, default=1 << 24,
+                    help="grid nodes of the simulations the server admits at once (0: no limit; default "
+                         "2^24, a 4096^2 grid's worth, which fills the device)")
     ap.add_argument("--serving-batched-only", action="store_true",
                     help="replay the stream batched only, without the one-simulation-per-launch comparison "
                          "(profiling runs)")
@@ -364,7 +367,7 @@ def decay_fit_args(entry, kw):
     return 2 * k * k, (omega if omega * kw["nsteps"] * kw["dt"] >= 4 * math.pi else 0.0)
 
 
-def serving_bench(n_requests, every, batched_only=False):
+def serving_bench(n_requests, every, batched_only=False, node_limit=0):
     """Replay the first n_requests of the seeded serving stream (Poisson
     arrivals, mean gap 2 ms; square grids 64..1024; CS D2Q9 or FD D2Q16;
     500-5000 steps) twice on the GPU: batched (lb_server, continuous
@@ -385,7 +388,7 @@ def serving_bench(n_requests, every, batched_only=False):
     n = len(trace)
 
     # batched, continuous admission
-    srv = serve.Server(hbm_budget_bytes=200 << 30, max_slots=512, chunk_steps=32)
+    srv = serve.Server(hbm_budget_bytes=200 << 30, max_slots=512, chunk_steps=32, node_limit=node_limit)
     results = {}
     t0 = time.perf_counter()
     c0 = srv.clock()
@@ -412,6 +415,7 @@ def serving_bench(n_requests, every, batched_only=False):
                "service_p99_s": round(float(np.percentile(svc_b, 99)), 4),
                "mlups": round(sum(kw["Nx"] * kw["Ny"] * kw["nsteps"] for kw in reqs) / wall_b / 1e6, 1),
                "batch_steps": stats["batch_steps"]}
+    batched["node_limit"] = node_limit
     if batched_only:
         return {"requests": n, "batched": batched}
 
@@ -653,7 +657,8 @@ def main():
         if args.only is not None or args.no_cache_free:
             cs.destroy()
             fd.destroy()
-        line["serving"] = serving_bench(args.serving_requests, every, args.serving_batched_only)
+        line["serving"] = serving_bench(args.serving_requests, every, args.serving_batched_only,
+                                        args.serving_node_limit)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(every, n)
     print(json.dumps(line), flush=True)

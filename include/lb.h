@@ -393,6 +393,16 @@ lb_server *lb_server_create(size_t hbm_budget_bytes, int max_slots, int chunk_st
  * other than 0 and 1. */
 int lb_server_configure(lb_server *srv, int use_graphs, int tune_tiles);
 
+/* Admission by nodes in flight, before the first lb_server_submit (LB_ESTATE
+ * after it): queued requests are admitted (in arrival order, within the
+ * budget and slots) only while the grid nodes of the admitted simulations
+ * stay at or below max_nodes; a request larger than the limit is admitted
+ * alone.  0 (the default) sets no limit, so every request that fits the
+ * budget runs at once and all share the device.  A limit that still fills
+ * the device keeps the throughput and lets the earlier requests finish
+ * sooner (lower time-to-result).  LB_EINVAL for a NULL server. */
+int lb_server_set_node_limit(lb_server *srv, size_t max_nodes);
+
 /* Queue a request (non-blocking).  LB_EINVAL for a request that lb_create
  * would reject or that is not supported in a batch; LB_EBUSY when the
  * request alone exceeds the budget.  *id receives the request id. */

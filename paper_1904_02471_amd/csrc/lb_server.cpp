@@ -51,6 +51,7 @@ struct Pending {
     lb_request req;
     double t_submit;
     size_t footprint;
+    size_t nodes;  // Nx * Ny
 };
 
 struct Running {
@@ -58,7 +59,7 @@ struct Running {
     lb_sim *sim;
     int start_epoch, nsteps, every;
     double t_submit, t_admit;
-    size_t footprint;
+    size_t footprint, nodes;
     int N;  // FD equilibrium order (0 for CS)
     double dt, decay_k2, decay_omega;  // viscosity fit of the amplitude series (decay_k2 > 0)
 };
@@ -120,6 +121,10 @@ struct lb_server {
     int device = 0;
     bool use_graphs = true;  // replay each batched step as a captured graph
     bool tune_tiles = true;  // time the later-stage tile heights per FD order
+    // nodes of the simulations admitted at once (0: no limit): enough to
+    // fill the device keeps the throughput, and fewer simulations sharing it
+    // finish the earlier requests sooner
+    size_t node_limit = 0;
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -133,6 +138,7 @@ struct lb_server {
     // worker-owned state
     std::vector<Running> running;
     size_t used = 0;
+    size_t nodes_in = 0;  // nodes of the admitted simulations
     hipStream_t stream = nullptr;   // batched steps
     hipStream_t astream = nullptr;  // admission: create and initialise new simulations
     hipEvent_t chunk_done = nullptr;
@@ -226,6 +232,7 @@ int lb_server::admit(const Pending &p)
     r.t_submit = p.t_submit;
     r.t_admit = now_s(t0);
     r.footprint = p.footprint;
+    r.nodes = p.nodes;
     r.N = sim->cs ? 0 : sim->N;
     r.dt = q.dt;
     r.decay_k2 = q.decay_k2;
@@ -449,6 +456,7 @@ void lb_server::drain()
         }
         lb_destroy(s);
         used -= r.footprint;
+        nodes_in -= r.nodes;
         finish(r.id, r.tag, status, r.t_submit, r.t_admit, std::move(rows), nu);
     }
     running.swap(keep);
@@ -462,6 +470,7 @@ void lb_server::fail_all(int rc)
     for (Running &r : running) {
         lb_destroy(r.sim);
         used -= r.footprint;
+        nodes_in -= r.nodes;
         finish(r.id, r.tag, rc, r.t_submit, r.t_admit, {}, std::nan(""));
     }
     running.clear();
@@ -476,8 +485,11 @@ void lb_server::run()
         {
             std::unique_lock<std::mutex> lk(mu);
             while (!queue.empty() && (int)(running.size() + admit_now.size()) < max_slots &&
-                   used + queue.front().footprint <= budget) {
+                   used + queue.front().footprint <= budget &&
+                   (node_limit == 0 || running.size() + admit_now.size() == 0 ||
+                    nodes_in + queue.front().nodes <= node_limit)) {
                 used += queue.front().footprint;
+                nodes_in += queue.front().nodes;
                 admit_now.push_back(queue.front());
                 queue.pop_front();
             }
@@ -493,6 +505,7 @@ void lb_server::run()
             const int rc = admit(p);
             if (rc != LB_OK) {
                 used -= p.footprint;
+                nodes_in -= p.nodes;
                 finish(p.id, p.req.tag, rc, p.t_submit, now_s(t0), {}, std::nan(""));
             } else {
                 changed = true;
@@ -572,6 +585,15 @@ int lb_server_configure(lb_server *s, int use_graphs, int tune_tiles)
     return LB_OK;
 }
 
+int lb_server_set_node_limit(lb_server *s, size_t max_nodes)
+{
+    if (!s) return set_last_error(LB_EINVAL);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->started.load()) return set_last_error(LB_ESTATE);
+    s->node_limit = max_nodes;
+    return LB_OK;
+}
+
 int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
 {
     if (!s || !req || !req->rho || !req->ux || !req->uy || req->nsteps < 1 || req->sample_every < 1 ||
@@ -590,6 +612,7 @@ int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
     Pending p{};
     p.req = *req;
     p.footprint = footprint_of(*req, mi);
+    p.nodes = (size_t)req->Nx * (size_t)req->Ny;
     if (p.footprint > s->budget) return set_last_error(LB_EBUSY);
     std::lock_guard<std::mutex> lk(s->mu);
     if (!s->started.exchange(true)) s->worker = std::thread([s] { s->run(); });

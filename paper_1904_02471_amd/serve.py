@@ -45,6 +45,8 @@ _lib.lb_server_stats.restype = ctypes.c_int
 _lib.lb_server_stats.argtypes = [ctypes.c_void_p, _dp]
 _lib.lb_server_configure.restype = ctypes.c_int
 _lib.lb_server_configure.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+_lib.lb_server_set_node_limit.restype = ctypes.c_int
+_lib.lb_server_set_node_limit.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
 _lib.lb_fit_decay.restype = ctypes.c_int
 _lib.lb_fit_decay.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp]
 _lib.lb_server_destroy.restype = None
@@ -59,7 +61,8 @@ class Server:
     """Python handle of an lb_server.  Keeps the host arrays of every
     submitted request alive until its result is polled."""
 
-    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=512, chunk_steps=32, use_graphs=True, tune_tiles=True):
+    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=512, chunk_steps=32, use_graphs=True, tune_tiles=True,
+                 node_limit=0):
         h = _lib.lb_server_create(int(hbm_budget_bytes), int(max_slots), int(chunk_steps))
         if not h:
             raise lb.LBError(lb.lb_last_error(), "lb_server_create")
@@ -68,6 +71,9 @@ class Server:
         rc = _lib.lb_server_configure(h, int(bool(use_graphs)), int(bool(tune_tiles)))
         if rc != lb.LB_OK:
             raise lb.LBError(rc, "lb_server_configure")
+        rc = _lib.lb_server_set_node_limit(h, int(node_limit))
+        if rc != lb.LB_OK:
+            raise lb.LBError(rc, "lb_server_set_node_limit")
 
     def submit(self, model, Nx, Ny, tau, dt, ds, N, rho, ux, uy, nsteps, sample_every, probe=None, tag=0,
                decay_k2=0.0, decay_omega=0.0):

@@ -240,3 +240,39 @@ def test_a_diverging_request_fails_alone():
     with pytest.raises(lb.LBError) as err:
         g.reduce()
     assert err.value.code == lb.LB_ENAN
+
+
+def test_node_limit_admits_in_arrival_order():
+    """With a limit on the nodes in flight the server admits queued requests
+    in arrival order only while the admitted grids fit the limit (a request
+    larger than it alone), and every result still equals its single run bit
+    for bit; the limit is set before the first submission only."""
+    print("case: serving node limit", flush=True)
+    entries = [{"kind": "tgv", "side": 64, "model": "cs", "tau_std": 0.7, "steps": 90},
+               {"kind": "shear", "side": 64, "model": "fd16", "tau_std": 0.9, "steps": 30},
+               {"kind": "tgv", "side": 64, "model": "fd16", "tau_std": 0.6, "steps": 20},
+               {"kind": "tgv", "side": 96, "model": "cs", "tau_std": 0.8, "steps": 40},
+               {"kind": "shear", "side": 64, "model": "cs", "tau_std": 1.2, "steps": 25}]
+    srv = serve.Server(8 << 30, 64, 8, node_limit=2 * 64 * 64)
+    fields = serve.field_cache()
+    for i, e in enumerate(entries):
+        srv.submit(sample_every=EVERY, tag=i, **serve.trace_request(e, fields))
+    assert serve._lib.lb_server_set_node_limit(srv._h, 0) == lb.LB_ESTATE
+    peak = 0
+    t_end = time.time() + 120
+    res = {}
+    while len(res) < len(entries):
+        assert time.time() < t_end, "results missing"
+        peak = max(peak, srv.stats()["running"])
+        for r in srv.poll(16, 1000):
+            res[r["tag"]] = r
+    srv.close()
+    assert peak <= 2
+    for i, e in enumerate(entries):
+        assert res[i]["status"] == 0
+        assert np.array_equal(res[i]["samples"], single_run(e)), e
+    # arrival order: the third request waits for one of the first two, the
+    # 96^2 request (above the limit with anything else) runs alone
+    assert res[2]["t_admit"] >= min(res[0]["t_finish"], res[1]["t_finish"])
+    others = [res[i] for i in (0, 1, 2, 4)]
+    assert all(o["t_finish"] <= res[3]["t_admit"] or o["t_admit"] >= res[3]["t_finish"] for o in others)
