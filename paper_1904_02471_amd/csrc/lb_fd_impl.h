@@ -186,6 +186,18 @@ struct FdPlaneIO<__half> {
     }
 };
 
+
+// Sign tests of a velocity component held in a scalar register, on its bits
+// (integer compares run on the scalar unit; float compares would take vector
+// instructions): non-zero, and positive.
+__device__ __forceinline__ bool v_nonzero(float v) { return (__builtin_bit_cast(uint32_t, v) & 0x7fffffffu) != 0u; }
+__device__ __forceinline__ bool v_positive(float v) { return __builtin_bit_cast(int32_t, v) > 0; }
+__device__ __forceinline__ bool v_nonzero(double v)
+{
+    return (__builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull) != 0ull;
+}
+__device__ __forceinline__ bool v_positive(double v) { return __builtin_bit_cast(int64_t, v) > 0; }
+
 __device__ __forceinline__ int fd_wrap(int v, int n)
 {
     int r = v % n;
@@ -310,6 +322,11 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 
     const int tid = threadIdx.x;
     const int lx = tid & 63, wy = tid >> 6;
+    // the wave's first thread and row block as scalars, so that the LDS
+    // destinations of the tile copies (wave-uniform) are formed in scalar
+    // registers
+    const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;
+    const int wy_s = wave0 >> 6;
     const int cw = diag_block & 3;  // wave of the column-0 x-faces
     // that wave has the tile-edge faces to evaluate on top of its share, and
     // the others wait for it at the barriers: let its instructions go first
@@ -363,7 +380,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     // the vector-memory counter
     auto fetch_lds = [&](int k, int buf) {
         const auto sk = fd_plane(src + k * P, pbytes);
-        const int wave_base = tid & ~63;
+        const int wave_base = wave0;  // wave-uniform (scalar) LDS offset of the wave
 #pragma unroll
         for (int i = 0; i < kLoadsPerThread; ++i) {
             const uint32_t o = toff[i];
@@ -466,6 +483,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         const int buf = k & 1;
         const CT *L = tile[buf];
         const CT vxk = p.vx[k], vyk = p.vy[k];
+        const bool xnz = v_nonzero(vxk), xpos = v_positive(vxk), ynz = v_nonzero(vyk), ypos = v_positive(vyk);
 
         CT gnv[kRows];
         if constexpr (kDma) {
@@ -473,7 +491,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 const auto gk = fd_plane(gn + k * P, pbytes);
 #pragma unroll
                 for (int r = 0; r < kRows; ++r)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(gk, &gnl[(wy * kRows + r) * kTX], 4, node_off(r), 0, 0, 0);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(gk, &gnl[(wy_s * kRows + r) * kTX], 4, node_off(r), 0, 0, 0);
             }
             if (k + 1 < p.K) fetch_lds(k + 1, buf ^ 1);
         } else if (WITH_GN) {
@@ -486,10 +504,10 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         //    tile columns i-1 and i), marching; column-0 faces by kTY lanes of
         //    wave cw (rotating with the tile, so that no SIMD takes them for
         //    every workgroup)
-        if (vxk != CT(0)) {
+        if (xnz) {
             CT w[kSeg + 4];
             CT *fx = &xface[xr * kXFaceStride + xs * kSeg + 1];
-            if (vxk > CT(0)) {
+            if (xpos) {
 #pragma unroll
                 for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 2 + i];
 #pragma unroll
@@ -516,11 +534,11 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         //    LDS, and the tile's bottom faces come from wave cw
         CT dfy[kRows];
         CT g1 = CT(0);  // face 1, paired with face 0 after the barrier
-        if (vyk != CT(0)) {
+        if (ynz) {
             CT w[kRows + 4];
             CT prev = CT(0);
             const int c00 = kHalo * kLX + lx + kHalo;  // LDS cell of the column's tile row 0
-            if (vyk > CT(0)) {
+            if (ypos) {
 #pragma unroll
                 for (int i = 0; i < kRows + 4; ++i) w[i] = L[c0 + (i - 2) * kLX];
 #pragma unroll
@@ -556,7 +574,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         }
         if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
         __syncthreads();
-        if (vyk != CT(0)) dfy[0] = g1 - yface[wy * kTX + lx];
+        if (ynz) dfy[0] = g1 - yface[wy * kTX + lx];
 
         // c. node updates
         const auto ok = fd_plane(out + k * P, pbytes);
@@ -574,7 +592,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         for (int r = 0; r < kRows; ++r) {
             const int tr = wy * kRows + r;  // tile row
             const CT g = L[c0 + r * kLX];
-            const CT dfx = (vxk != CT(0)) ? xface[tr * kXFaceStride + lx + 1] - xface[tr * kXFaceStride + lx] : CT(0);
+            const CT dfx = xnz ? xface[tr * kXFaceStride + lx + 1] - xface[tr * kXFaceStride + lx] : CT(0);
 
             const CT geq = fd_geq<CT, N>(wk, hx, hy, p.rho0, drho[r], uxv[r], uyv[r], dltl[r * kFdThreads + tid]);
 
