@@ -11,6 +11,7 @@
 
 #include "lb_diag.h"
 #include "lb_internal.h"
+#include "lb_node_index.h"
 
 namespace lbm {
 
@@ -85,7 +86,10 @@ __device__ __forceinline__ double ref_shift(const Params<double> &p, int k, int 
     if (!p.ref) return 0.0;
     float ux, uy;
     ref_unpack(p.ref[(long long)ys * p.pitch + xs], ux, uy);
-    return (double)cs_ref_pop(k, ux, uy, p.ref_c);
+    float c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = p.ref_c[i];
+    return (double)cs_ref_pop(k, ux, uy, c);
 }
 
 // Shifted value g_k = f_k - w_k rho0 of the canonical state at (x, y) (under
@@ -120,7 +124,8 @@ __global__ __launch_bounds__(kAuxThreads) void ref_from_velocity_kernel(uint32_t
 {
     const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
     if (n >= (long long)p.Nx * p.Ny) return;
-    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    int x, y;
+    node_xy(n, p.Nx, x, y);
     const unsigned short hx = __builtin_bit_cast(unsigned short, (_Float16)(ux[n] * inv_cl));
     const unsigned short hy = __builtin_bit_cast(unsigned short, (_Float16)(uy[n] * inv_cl));
     ref[(long long)y * p.pitch + x] = (uint32_t)hx | ((uint32_t)hy << 16);
@@ -133,7 +138,8 @@ __global__ __launch_bounds__(kAuxThreads) void ref_from_state_kernel(uint32_t *r
     const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
     const long long nodes = (long long)p.Nx * p.Ny;
     if (n >= nodes) return;
-    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    int x, y;
+    node_xy(n, p.Nx, x, y);
     double r = 0.0, jx = 0.0, jy = 0.0;
     for (int k = 0; k < p.K; ++k) {
         const double fk = f[k * nodes + n];
@@ -152,7 +158,8 @@ __global__ __launch_bounds__(kAuxThreads) void init_kernel(T *dst, const double 
 {
     const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
     if (n >= (long long)p.Nx * p.Ny) return;
-    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    int x, y;
+    node_xy(n, p.Nx, x, y);
     const double r = rho[n];
     const double ax = ux[n] / p.cs, ay = uy[n] / p.cs;
     for (int k = 0; k < p.K; ++k) store_g(dst, p, cs, k, x, y, feq_shifted(p, k, r - p.rho0, r, ax, ay));
@@ -176,7 +183,8 @@ __global__ __launch_bounds__(kAuxThreads) void get_state_kernel(const T *src, do
     const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
     const long long nodes = (long long)p.Nx * p.Ny;
     if (n >= nodes) return;
-    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    int x, y;
+    node_xy(n, p.Nx, x, y);
     for (int k = 0; k < p.K; ++k) f[k * nodes + n] = stored_g(src, p, cs, k, x, y) + p.w[k] * p.rho0;
 }
 
@@ -187,7 +195,8 @@ __global__ __launch_bounds__(kAuxThreads) void set_state_kernel(T *dst, const do
     const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
     const long long nodes = (long long)p.Nx * p.Ny;
     if (n >= nodes) return;
-    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    int x, y;
+    node_xy(n, p.Nx, x, y);
     for (int k = 0; k < p.K; ++k) store_g(dst, p, cs, k, x, y, f[k * nodes + n] - p.w[k] * p.rho0);
 }
 
@@ -211,7 +220,8 @@ __global__ __launch_bounds__(kAuxThreads) void moments_kernel(const T *src, doub
 {
     const long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x;
     if (n >= (long long)p.Nx * p.Ny) return;
-    const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+    int x, y;
+    node_xy(n, p.Nx, x, y);
     double drho, jx, jy;
     node_moments(src, cs, p, x, y, drho, jx, jy);
     const double r = p.rho0 + drho;
@@ -228,7 +238,8 @@ __global__ __launch_bounds__(kAuxThreads) void reduce_kernel(const T *src, bool 
     DiagAcc acc;
     for (long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x; n < nodes;
          n += (long long)gridDim.x * kAuxThreads) {
-        const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+        int x, y;
+        node_xy(n, p.Nx, x, y);
         double drho, jx, jy;
         node_moments(src, cs, p, x, y, drho, jx, jy);
         const double r = p.rho0 + drho, ux = jx / r, uy = jy / r;
@@ -258,7 +269,8 @@ __global__ __launch_bounds__(kAuxThreads) void reduce_field_kernel(const T *src,
     double acc[kDiag + 1] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (long long n = (long long)blockIdx.x * kAuxThreads + threadIdx.x; n < nodes;
          n += (long long)gridDim.x * kAuxThreads) {
-        const int x = (int)(n % p.Nx), y = (int)(n / p.Nx);
+        int x, y;
+        node_xy(n, p.Nx, x, y);
         double drho, jx, jy;
         node_moments(src, cs, p, x, y, drho, jx, jy);
         const double r = p.rho0 + drho, ux = jx / r, uy = jy / r;

@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "lb_fd_impl.h"
+#include "lb_node_index.h"
 
 namespace lbm {
 
@@ -57,7 +58,9 @@ __global__ __launch_bounds__(256) void fd_moments_kernel(T *g, const Params<type
     using CT = typename Arith<T>::type;
     const long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (node >= (long long)p.Nx * p.Ny) return;
-    const long long o = (node / p.Nx) * p.pitch + p.xoff + node % p.Nx;
+    int x, y;
+    node_xy(node, p.Nx, x, y);
+    const long long o = (long long)y * p.pitch + p.xoff + x;
     MomAcc<CT> m;
     for (int k = 0; k < p.K; ++k) m.add(p, k, ld(g + k * p.plane + o));
     m.store(p, g, o);
@@ -119,7 +122,9 @@ __global__ __launch_bounds__(256) void fd_imex_relax_kernel(const T *__restrict_
     using CT = typename Arith<T>::type;
     const long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (node >= (long long)p.Nx * p.Ny) return;
-    const long long o = (node / p.Nx) * p.pitch + p.xoff + node % p.Nx;
+    int x, y;
+    node_xy(node, p.Nx, x, y);
+    const long long o = (long long)y * p.pitch + p.xoff + x;
     const long long P = p.plane;
     const NodeEq<CT, N> q = node_eq<CT, N>(p, [&](int k) { return ld(g + k * P + o); });
     uint32_t rb = mix32((uint32_t)node, p.salt);
@@ -148,7 +153,9 @@ __global__ __launch_bounds__(256) void fd_imex_mid_kernel(T *__restrict__ yb, co
     using CT = typename Arith<T>::type;
     const long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (node >= (long long)p.Nx * p.Ny) return;
-    const long long o = (node / p.Nx) * p.pitch + p.xoff + node % p.Nx;
+    int x, y;
+    node_xy(node, p.Nx, x, y);
+    const long long o = (long long)y * p.pitch + p.xoff + x;
     const long long P = p.plane;
     auto hk = [&](int k) {
         const CT f1 = ld(f1b + k * P + o);
