@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--serving-node-limit", type=int, default=1 << 24,
                     help="grid nodes of the simulations the server admits at once (0: no limit; default "
                          "2^24, a 4096^2 grid's worth, which fills the device)")
+    ap.add_argument("--serving-policy", choices=["arrival", "shortest"], default="arrival",
+                    help="admission order of the server (arrival order, or smallest estimated work first)")
     ap.add_argument("--serving-batched-only", action="store_true",
                     help="replay the stream batched only, without the one-simulation-per-launch comparison "
                          "(profiling runs)")
@@ -367,7 +369,7 @@ def decay_fit_args(entry, kw):
     return 2 * k * k, (omega if omega * kw["nsteps"] * kw["dt"] >= 4 * math.pi else 0.0)
 
 
-def serving_bench(n_requests, every, batched_only=False, node_limit=0):
+def serving_bench(n_requests, every, batched_only=False, node_limit=0, policy=0):
     """Replay the first n_requests of the seeded serving stream (Poisson
     arrivals, mean gap 2 ms; square grids 64..1024; CS D2Q9 or FD D2Q16;
     500-5000 steps) twice on the GPU: batched (lb_server, continuous
@@ -388,7 +390,8 @@ def serving_bench(n_requests, every, batched_only=False, node_limit=0):
     n = len(trace)
 
     # batched, continuous admission
-    srv = serve.Server(hbm_budget_bytes=200 << 30, max_slots=512, chunk_steps=32, node_limit=node_limit)
+    srv = serve.Server(hbm_budget_bytes=200 << 30, max_slots=512, chunk_steps=32, node_limit=node_limit,
+                       policy=policy)
     results = {}
     t0 = time.perf_counter()
     c0 = srv.clock()
@@ -416,8 +419,13 @@ def serving_bench(n_requests, every, batched_only=False, node_limit=0):
                "mlups": round(sum(kw["Nx"] * kw["Ny"] * kw["nsteps"] for kw in reqs) / wall_b / 1e6, 1),
                "batch_steps": stats["batch_steps"]}
     batched["node_limit"] = node_limit
+    batched["admission"] = "shortest estimated work first" if policy else "arrival order"
     if batched_only:
         return {"requests": n, "batched": batched}
+    # the same stream batched with shortest-estimated-work-first admission
+    # (the one-simulation-per-launch side below keeps arrival order, as the
+    # batched line above)
+    shortest = serving_bench(n_requests, every, True, node_limit, 1)["batched"] if policy == 0 else None
 
     # one simulation per launch sequence
     lat_s = np.zeros(n)
@@ -460,6 +468,7 @@ def serving_bench(n_requests, every, batched_only=False, node_limit=0):
         "requests": n, "stream": "seed 1904, Poisson arrivals mean 2 ms, side U{64..1024}, CS D2Q9 / FD D2Q16 "
                                   "50/50, tau U[0.55,1.5], steps U{500..5000}, FP32, diagnostics every %d" % every,
         "batched": batched,
+        "batched_shortest_first": shortest,
         "one_sim_per_launch": {"sims_per_s": round(n / wall_s, 3), "wall_s": round(wall_s, 3),
                                "p50_s": pct(lat_s, 50), "p99_s": pct(lat_s, 99),
                                "service_p50_s": pct(svc_s, 50), "service_p99_s": pct(svc_s, 99),
@@ -658,7 +667,7 @@ def main():
             cs.destroy()
             fd.destroy()
         line["serving"] = serving_bench(args.serving_requests, every, args.serving_batched_only,
-                                        args.serving_node_limit)
+                                        args.serving_node_limit, 1 if args.serving_policy == "shortest" else 0)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(every, n)
     print(json.dumps(line), flush=True)

@@ -403,6 +403,17 @@ int lb_server_configure(lb_server *srv, int use_graphs, int tune_tiles);
  * sooner (lower time-to-result).  LB_EINVAL for a NULL server. */
 int lb_server_set_node_limit(lb_server *srv, size_t max_nodes);
 
+/* Admission order of queued requests, before the first lb_server_submit
+ * (LB_ESTATE after it): LB_ADMIT_ARRIVAL (the default) admits in arrival
+ * order; LB_ADMIT_SHORTEST admits the request of smallest estimated device
+ * work first (grid nodes x steps x the model's cost per node-step: 1 for CS
+ * D2Q9, 0.75 K for an FD model of K populations), equal work in arrival
+ * order.  Shortest-first lowers the median time-to-result when many
+ * requests wait; a long request waits while shorter ones keep arriving.
+ * Results do not depend on the order.  LB_EINVAL for another value. */
+enum lb_admit_policy { LB_ADMIT_ARRIVAL = 0, LB_ADMIT_SHORTEST = 1 };
+int lb_server_set_policy(lb_server *srv, int policy);
+
 /* Queue a request (non-blocking).  LB_EINVAL for a request that lb_create
  * would reject or that is not supported in a batch; LB_EBUSY when the
  * request alone exceeds the budget.  *id receives the request id. */

@@ -52,6 +52,7 @@ struct Pending {
     double t_submit;
     size_t footprint;
     size_t nodes;  // Nx * Ny
+    double work;   // estimated device work: nodes x steps x the model's cost per node-step
 };
 
 struct Running {
@@ -125,6 +126,8 @@ struct lb_server {
     // fill the device keeps the throughput, and fewer simulations sharing it
     // finish the earlier requests sooner
     size_t node_limit = 0;
+    // admission order: arrival (0) or smallest estimated work first (1)
+    int policy = 0;
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -484,6 +487,10 @@ void lb_server::run()
         std::vector<Pending> admit_now;
         {
             std::unique_lock<std::mutex> lk(mu);
+            if (policy == 1 && queue.size() > 1)
+                // smallest estimated work first; equal work in arrival order
+                std::stable_sort(queue.begin(), queue.end(),
+                                 [](const Pending &a, const Pending &b) { return a.work < b.work; });
             while (!queue.empty() && (int)(running.size() + admit_now.size()) < max_slots &&
                    used + queue.front().footprint <= budget &&
                    (node_limit == 0 || running.size() + admit_now.size() == 0 ||
@@ -585,6 +592,15 @@ int lb_server_configure(lb_server *s, int use_graphs, int tune_tiles)
     return LB_OK;
 }
 
+int lb_server_set_policy(lb_server *s, int policy)
+{
+    if (!s || (policy != LB_ADMIT_ARRIVAL && policy != LB_ADMIT_SHORTEST)) return set_last_error(LB_EINVAL);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->started.load()) return set_last_error(LB_ESTATE);
+    s->policy = policy;
+    return LB_OK;
+}
+
 int lb_server_set_node_limit(lb_server *s, size_t max_nodes)
 {
     if (!s) return set_last_error(LB_EINVAL);
@@ -613,6 +629,10 @@ int lb_server_submit(lb_server *s, const lb_request *req, uint64_t *id)
     p.req = *req;
     p.footprint = footprint_of(*req, mi);
     p.nodes = (size_t)req->Nx * (size_t)req->Ny;
+    // cost per node-step relative to a CS D2Q9 step: an FD step (three
+    // WENO-5 stages) over K populations costs ~0.75 K of them (12 for D2Q16,
+    // as the measured rates of the two kernels)
+    p.work = (double)p.nodes * (double)req->nsteps * (req->model == LB_CS_D2Q9 ? 1.0 : 0.75 * mi.K);
     if (p.footprint > s->budget) return set_last_error(LB_EBUSY);
     std::lock_guard<std::mutex> lk(s->mu);
     if (!s->started.exchange(true)) s->worker = std::thread([s] { s->run(); });

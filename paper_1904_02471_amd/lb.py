@@ -30,7 +30,7 @@ EXPORTS = ["lb_create", "lb_destroy", "lb_last_error", "lb_strerror", "lb_model_
            "lb_get_tuning", "lb_set_stream", "lb_synchronize",
            "lb_device_bytes",
            "lb_server_create", "lb_server_submit", "lb_server_poll", "lb_server_release", "lb_server_clock",
-           "lb_server_stats", "lb_server_destroy", "lb_server_configure", "lb_server_set_node_limit", "lb_fit_decay"]
+           "lb_server_stats", "lb_server_destroy", "lb_server_configure", "lb_server_set_node_limit", "lb_server_set_policy", "lb_fit_decay"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p

@@ -47,6 +47,9 @@ _lib.lb_server_configure.restype = ctypes.c_int
 _lib.lb_server_configure.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
 _lib.lb_server_set_node_limit.restype = ctypes.c_int
 _lib.lb_server_set_node_limit.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+_lib.lb_server_set_policy.restype = ctypes.c_int
+_lib.lb_server_set_policy.argtypes = [ctypes.c_void_p, ctypes.c_int]
+ADMIT_ARRIVAL, ADMIT_SHORTEST = 0, 1
 _lib.lb_fit_decay.restype = ctypes.c_int
 _lib.lb_fit_decay.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp]
 _lib.lb_server_destroy.restype = None
@@ -62,7 +65,7 @@ class Server:
     submitted request alive until its result is polled."""
 
     def __init__(self, hbm_budget_bytes=64 << 30, max_slots=512, chunk_steps=32, use_graphs=True, tune_tiles=True,
-                 node_limit=0):
+                 node_limit=0, policy=0):
         h = _lib.lb_server_create(int(hbm_budget_bytes), int(max_slots), int(chunk_steps))
         if not h:
             raise lb.LBError(lb.lb_last_error(), "lb_server_create")
@@ -74,6 +77,9 @@ class Server:
         rc = _lib.lb_server_set_node_limit(h, int(node_limit))
         if rc != lb.LB_OK:
             raise lb.LBError(rc, "lb_server_set_node_limit")
+        rc = _lib.lb_server_set_policy(h, int(policy))
+        if rc != lb.LB_OK:
+            raise lb.LBError(rc, "lb_server_set_policy")
 
     def submit(self, model, Nx, Ny, tau, dt, ds, N, rho, ux, uy, nsteps, sample_every, probe=None, tag=0,
                decay_k2=0.0, decay_omega=0.0):

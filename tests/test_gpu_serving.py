@@ -276,3 +276,36 @@ def test_node_limit_admits_in_arrival_order():
     assert res[2]["t_admit"] >= min(res[0]["t_finish"], res[1]["t_finish"])
     others = [res[i] for i in (0, 1, 2, 4)]
     assert all(o["t_finish"] <= res[3]["t_admit"] or o["t_admit"] >= res[3]["t_finish"] for o in others)
+
+
+def test_shortest_first_admission():
+    """LB_ADMIT_SHORTEST admits the queued request of smallest estimated work
+    (nodes x steps x the model's cost) first: with one simulation at a time,
+    the requests queued behind the first one finish in order of their work,
+    and every result equals its single run bit for bit."""
+    print("case: serving shortest first", flush=True)
+    entries = [{"kind": "tgv", "side": 64, "model": "cs", "tau_std": 0.7, "steps": 60},      # work 64^2 x 60
+               {"kind": "tgv", "side": 64, "model": "fd16", "tau_std": 0.9, "steps": 40},    # x 12 x 40
+               {"kind": "shear", "side": 64, "model": "cs", "tau_std": 1.1, "steps": 20},    # 20
+               {"kind": "tgv", "side": 64, "model": "cs", "tau_std": 0.8, "steps": 200},     # 200
+               {"kind": "shear", "side": 64, "model": "fd16", "tau_std": 0.6, "steps": 5}]   # 60
+    srv = serve.Server(8 << 30, 64, 8, node_limit=64 * 64, policy=serve.ADMIT_SHORTEST)
+    assert serve._lib.lb_server_set_policy(srv._h, 0) == lb.LB_OK  # before the first submission
+    assert serve._lib.lb_server_set_policy(srv._h, 2) == lb.LB_EINVAL
+    assert serve._lib.lb_server_set_policy(srv._h, serve.ADMIT_SHORTEST) == lb.LB_OK
+    fields = serve.field_cache()
+    kws = [serve.trace_request(e, fields) for e in entries]  # prepared first: the submissions follow at once
+    for i, kw in enumerate(kws):
+        srv.submit(sample_every=EVERY, tag=i, **kw)
+    assert serve._lib.lb_server_set_policy(srv._h, 0) == lb.LB_ESTATE
+    res = {r["tag"]: r for r in serve.wait_all(srv, len(entries), 120)}
+    srv.close()
+    for i, e in enumerate(entries):
+        assert res[i]["status"] == 0
+        assert np.array_equal(res[i]["samples"], single_run(e)), e
+    work = {i: 64 * 64 * e["steps"] * (12.0 if e["model"] == "fd16" else 1.0) for i, e in enumerate(entries)}
+    # the first request may be admitted before the others arrive; the rest
+    # run one at a time in order of work (ties: arrival)
+    later = sorted((i for i in range(len(entries)) if res[i]["t_admit"] > min(r["t_admit"] for r in res.values())),
+                   key=lambda i: res[i]["t_admit"])
+    assert [work[i] for i in later] == sorted(work[i] for i in later), later
