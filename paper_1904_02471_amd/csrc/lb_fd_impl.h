@@ -13,10 +13,11 @@
 // are written as g + c (x - g) so that the two weights sum to one exactly in
 // floating point (1/3 and 2/3 do not): no spurious growth of the state.
 //
-// The stage is bound by vector-ALU issue (the WENO-5 face is the bulk of the
-// work), so the mapping evaluates every face once and marches along rows and
-// columns so that neighbouring faces share their differences and smoothness
-// terms:
+// The WENO-5 face is the bulk of the arithmetic, so the mapping evaluates
+// every face once and marches along rows and columns so that neighbouring
+// faces share their differences and smoothness terms (the stage sits between
+// its memory traffic and the rate at which two waves co-issue its vector
+// instructions; neither is saturated):
 //
 //   A workgroup of 256 threads owns a 64 x 32 tile; thread (lx, wy) owns
 //   column lx and the 8 rows 8 wy .. 8 wy + 7 (the canonical geometry; the
