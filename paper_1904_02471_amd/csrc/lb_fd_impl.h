@@ -35,7 +35,8 @@
 //      b. y-faces: thread (lx, wy) marches up its column over the 8 faces
 //         above its 8 nodes, from a 12-value register window; the face
 //         below its first node is the top face of the thread below (LDS),
-//         the tile's bottom faces are computed by one wave;
+//         the tile's bottom faces are computed by another wave (the two
+//         edge tasks go to different waves, which rotate with the tile);
 //      c. node update: flux differences, order-N equilibrium of population
 //         k, Runge-Kutta combination, store; the stored values are summed
 //         into the output's moments, written after the last population.
@@ -328,10 +329,11 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
     // registers
     const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;
     const int wy_s = wave0 >> 6;
-    const int cw = diag_block & 3;  // wave of the column-0 x-faces
-    // that wave has the tile-edge faces to evaluate on top of its share, and
-    // the others wait for it at the barriers: let its instructions go first
-    if (wy == cw) __builtin_amdgcn_s_setprio(2);
+    const int cw = diag_block & 3;  // wave of the tile's bottom y-faces
+    const int cxw = cw ^ 2;         // wave of the column-0 x-faces
+    // those waves have the tile-edge faces to evaluate on top of their share,
+    // and the others wait for them at the barriers: let their instructions go first
+    if (wy == cw || wy == cxw) __builtin_amdgcn_s_setprio(2);
     const int x0 = bx * kTX, y0 = by * kTY;
     const int Nx = p.Nx, Ny = p.Ny;
     const long long P = p.plane;
@@ -503,8 +505,9 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 
         // a. x-faces: faces xs*8 + 1 .. xs*8 + 8 of row xr (face i lies between
         //    tile columns i-1 and i), marching; column-0 faces by kTY lanes of
-        //    wave cw (rotating with the tile, so that no SIMD takes them for
-        //    every workgroup)
+        //    wave cxw (rotating with the tile, so that no SIMD takes them for
+        //    every workgroup; not the wave of the bottom y-faces, so that no
+        //    wave holds both edge tasks up at the barrier)
         if (xnz) {
             CT w[kSeg + 4];
             CT *fx = &xface[xr * kXFaceStride + xs * kSeg + 1];
@@ -513,7 +516,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 2 + i];
 #pragma unroll
                 for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m], w[m + 1], w[m + 2], w[m + 3], w[m + 4], eps);
-                if (wy == cw && lx < kTY) {
+                if (wy == cxw && lx < kTY) {
                     const int b = (lx + kHalo) * kLX + kHalo - 1;  // upwind cell of the column-0 face
                     xface[lx * kXFaceStride] = weno5(L[b - 2], L[b - 1], L[b], L[b + 1], L[b + 2], eps);
                 }
@@ -522,7 +525,7 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                 for (int i = 0; i < kSeg + 4; ++i) w[i] = L[xw - 1 + i];
 #pragma unroll
                 for (int m = 0; m < kSeg; ++m) fx[m] = weno5(w[m + 4], w[m + 3], w[m + 2], w[m + 1], w[m], eps);
-                if (wy == cw && lx < kTY) {
+                if (wy == cxw && lx < kTY) {
                     const int b = (lx + kHalo) * kLX + kHalo;  // upwind cell of the column-0 face
                     xface[lx * kXFaceStride] = weno5(L[b + 2], L[b + 1], L[b], L[b - 1], L[b - 2], eps);
                 }

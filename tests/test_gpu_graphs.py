@@ -75,6 +75,7 @@ def test_graph_steps_argument_range():
     (lb.LB_CS_D2Q9, 100, 10, lb.LB_FP64, [(128, 8, 8)]),
     (lb.LB_FD_D2Q16, 70, 40, lb.LB_FP32, [(0, 4, 4), (0, 8, 4), (0, 4, 8)]),
     (lb.LB_FD_D2Q36, 65, 33, lb.LB_FP64, [(0, 4, 4), (0, 8, 4)]),
+    (lb.LB_FD_D2Q36, 70, 37, lb.LB_FP32, [(0, 4, 4), (0, 8, 4)]),
     (lb.LB_FD_D2Q16, 64, 48, lb.LB_FP16_SHIFTED, [(0, 4, 4), (0, 8, 4)]),
 ])
 def test_launch_shapes_do_not_change_results(model, Nx, Ny, prec, shapes):
