@@ -10,10 +10,11 @@ namespace lbm {
 namespace {
 
 // Occupancy asked of the compiler: five waves per SIMD (at most 96
-// registers) for the later-stage 64 x 16 kernels of order 4 with FP32
-// storage, which fit it without spills (left alone they take 105 registers
-// and four waves: D2Q36 steps 2 % slower; orders 1-3 take at most 95 by
-// themselves, order 5 spills at 96).  Nothing for the others: with the
+// registers) for the later-stage 64 x 16 kernel of order 3 with FP32
+// storage, which fits it without spills (left alone it takes 98 registers
+// and four waves since the base-value copy moved behind the x-face reads).
+// Order 4 spills at 96 registers in that form and keeps four waves (106
+// registers); order 5 spills at 96 too.  Nothing for the others: with the
 // moments of the output accumulated in registers, holding the 64 x 32
 // first-stage kernels to 128 registers (four waves per SIMD) spills and
 // runs slower than three waves without spills; the first-stage 64 x 16
@@ -21,7 +22,7 @@ namespace {
 // both ran slower than without the limit.
 template <typename T, int N, bool FIXED, bool DIAG, bool WITH_GN, int ROWS>
 __global__ __launch_bounds__(kFdThreads)
-__attribute__((amdgpu_waves_per_eu((WITH_GN && ROWS == 4 && N == 4 && sizeof(T) == 4) ? 5 : 1))) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
+__attribute__((amdgpu_waves_per_eu((WITH_GN && ROWS == 4 && N == 3 && sizeof(T) == 4) ? 5 : 1))) void fd_stage_kernel(const T *__restrict__ src, const T *gn, T *out,
                                                               const typename Arith<T>::type cb,
                                                               const Params<typename Arith<T>::type> p,
                                                               const DiagArgs<typename Arith<T>::type> d)

@@ -133,7 +133,9 @@ __device__ __forceinline__ CT weno5(CT a, CT b, CT c, CT d, CT e, CT eps)
 // per-lane 64-bit addresses held across the population loop.  Planes are
 // below 4 GiB (the library refuses larger finite-difference grids); the
 // descriptor's range is the plane's size, so an access past it would read
-// 0 or be dropped instead of touching other memory.
+// 0 or be dropped instead of touching other memory (the 64 x 32 stage uses
+// that to drop the stores of lanes without a node, at the offset of the
+// plane's end).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t fd_plane(const void *base, uint32_t nbytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
@@ -490,12 +492,6 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 
         CT gnv[kRows];
         if constexpr (kDma) {
-            if (WITH_GN) {
-                const auto gk = fd_plane(gn + k * P, pbytes);
-#pragma unroll
-                for (int r = 0; r < kRows; ++r)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(gk, &gnl[(wy_s * kRows + r) * kTX], 4, node_off(r), 0, 0, 0);
-            }
             if (k + 1 < p.K) fetch_lds(k + 1, buf ^ 1);
         } else if (WITH_GN) {
             const auto gk = fd_plane(gn + k * P, pbytes);
@@ -529,6 +525,21 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
                     const int b = (lx + kHalo) * kLX + kHalo;  // upwind cell of the column-0 face
                     xface[lx * kXFaceStride] = weno5(L[b + 2], L[b + 1], L[b], L[b - 1], L[b - 2], eps);
                 }
+            }
+        }
+
+        // the Runge-Kutta base values of population k, copied into LDS after
+        // the x-face window reads are issued: the compiler cannot tell those
+        // window reads from the copy's LDS writes and would wait for every
+        // copy in flight before them (the next tile's included), which
+        // serialised each population on its prefetch (y-face and node-update
+        // reads are told apart; the copy lands by the mid-population wait)
+        if constexpr (kDma) {
+            if (WITH_GN) {
+                const auto gk = fd_plane(gn + k * P, pbytes);
+#pragma unroll
+                for (int r = 0; r < kRows; ++r)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(gk, &gnl[(wy_s * kRows + r) * kTX], 4, node_off(r), 0, 0, 0);
             }
         }
 
@@ -576,15 +587,10 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
 #pragma unroll
             for (int r = 0; r < kRows; ++r) dfy[r] = CT(0);
         }
-        if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
-        __syncthreads();
-        if (ynz) dfy[0] = g1 - yface[wy * kTX + lx];
-
-        // c. node updates
-        const auto ok = fd_plane(out + k * P, pbytes);
+        // the population's table values: their scalar loads are issued
+        // before the mid-population wait, which covers their latency
         const int qi = p.ki[k], qj = p.kj[k];
         const CT wk = p.w[k];
-        const CT vxs = vxk * p.inv_ds, vys = vyk * p.inv_ds;
         CT hx[N + 1], hy[N + 1];
         hx[0] = hy[0] = CT(1);
 #pragma unroll
@@ -592,11 +598,23 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             hx[n] = p.hc[qi][n];
             hy[n] = p.hc[qj][n];
         }
+        if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
+        __syncthreads();
+        if (ynz) dfy[0] = g1 - yface[wy * kTX + lx];
+
+        // c. node updates
+        const auto ok = fd_plane(out + k * P, pbytes);
+        const CT vxs = vxk * p.inv_ds, vys = vyk * p.inv_ds;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             const int tr = wy * kRows + r;  // tile row
             const CT g = L[c0 + r * kLX];
-            const CT dfx = xnz ? xface[tr * kXFaceStride + lx + 1] - xface[tr * kXFaceStride + lx] : CT(0);
+            // both faces are read whatever v_kx, and the difference is taken
+            // by a select: a branch per row kept the compiler from overlapping
+            // the rows' LDS reads (with v_kx = 0 the x-face array holds another
+            // population's faces, or nothing yet, and the select drops them)
+            const CT fr = xface[tr * kXFaceStride + lx + 1], fl = xface[tr * kXFaceStride + lx];
+            const CT dfx = xnz ? fr - fl : CT(0);
 
             const CT geq = fd_geq<CT, N>(wk, hx, hy, p.rho0, drho[r], uxv[r], uyv[r], dltl[r * kFdThreads + tid]);
 
@@ -619,7 +637,15 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
             orho[r] += st;
             ojx[r] = fmaT(st, vxk, ojx[r]);
             ojy[r] = fmaT(st, vyk, ojy[r]);
-            if (active(r)) IO::put(ok, node_off(r), bits);
+            if constexpr (ROWS == 8) {
+                // lanes without a node here store past the plane's end, which
+                // the buffer resource's range check drops: no branch per row,
+                // so the rows' LDS reads overlap (64 x 16 tiles: the compiler
+                // then spills at the five-wave register limit)
+                IO::put(ok, active(r) ? node_off(r) : pbytes, bits);
+            } else if (active(r)) {
+                IO::put(ok, node_off(r), bits);
+            }
         }
         // the output's moments, after its last population (inside the loop:
         // stored after it, they kept other registers live and cost more)
