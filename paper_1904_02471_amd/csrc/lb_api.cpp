@@ -334,46 +334,35 @@ hipError_t plain_steps(lb_sim *s, long long n)
 
 // ---------------------------------------------------------------------
 // Autotuning of the plain-step launch shapes.  Candidates are timed on the
-// handle's own buffers with launches that leave the state untouched: a CS
+// handle's own buffers with launches that leave the state untouched.  CS: a
 // step from the current buffer into the other one (which the next step
-// overwrites), FD stage 1 into the stage buffer A or stage 2 from A into B.
-// fd_stage selects the FD stage timed (its tile rows fd_rows); cs_nt the CS
-// store policy.  With `scratch` (a device buffer of the handle's buffer
-// size) the timed CS launches ping-pong between the other buffer and it, as
-// consecutive steps do, so that each launch reads what the previous one
-// wrote: whether that is still in the last-level cache is what the store
-// policy changes.
+// overwrites) with workgroup size cs_threads and store policy cs_nt.  With
+// `scratch` (a device buffer of the handle's buffer size) the timed CS
+// launches ping-pong between the other buffer and it, as consecutive steps
+// do, so that each launch reads what the previous one wrote: whether that is
+// still in the last-level cache is what the store policy changes.
 template <typename T>
-hipError_t time_candidate(lb_sim *s, int cs_threads, bool cs_nt, int fd_stage, int fd_rows, int reps, float *ms,
-                          void *scratch = nullptr)
+hipError_t time_candidate(lb_sim *s, int cs_threads, bool cs_nt, int reps, float *ms, void *scratch = nullptr)
 {
     using CT = typename Arith<T>::type;
     const Params<CT> p = make_params<CT>(s);
-    T *g = s->cs ? nullptr : bufp<T>(s, 0), *a = s->cs ? nullptr : bufp<T>(s, 1), *b = s->cs ? nullptr : bufp<T>(s, 2);
     int nlaunch = 0;
     auto launch = [&]() -> hipError_t {
-        if (s->cs) {
-            const T *src = bufp<T>(s, s->cur);
-            T *dst = bufp<T>(s, 1 - s->cur);
-            if (scratch && nlaunch > 0) {
-                // other -> scratch, scratch -> other, ...
-                T *x = bufp<T>(s, 1 - s->cur), *y = static_cast<T *>(scratch);
-                src = (nlaunch & 1) ? x : y;
-                dst = (nlaunch & 1) ? y : x;
-            }
-            ++nlaunch;
-            return launch_cs_step_st<T>(src, dst, p, nullptr, s->stream, cs_threads, cs_nt);
+        const T *src = bufp<T>(s, s->cur);
+        T *dst = bufp<T>(s, 1 - s->cur);
+        if (scratch && nlaunch > 0) {
+            // other -> scratch, scratch -> other, ...
+            T *x = bufp<T>(s, 1 - s->cur), *y = static_cast<T *>(scratch);
+            src = (nlaunch & 1) ? x : y;
+            dst = (nlaunch & 1) ? y : x;
         }
-        if (fd_stage == 1) return launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, fd_rows);
-        return launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, fd_rows);
+        ++nlaunch;
+        return launch_cs_step_st<T>(src, dst, p, nullptr, s->stream, cs_threads, cs_nt);
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // warm-up; a later stage reads A, which a first stage fills
-    if (e == hipSuccess && !s->cs && fd_stage != 1)
-        e = launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, 8);
-    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = launch();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
     for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
@@ -381,6 +370,57 @@ hipError_t time_candidate(lb_sim *s, int cs_threads, bool cs_nt, int fd_stage, i
     if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    return e;
+}
+
+// Tile heights of the FD stage launches timed against each other over whole
+// steps: blocks of `block` consecutive steps per candidate (first-stage rows,
+// later-stage rows), the candidates taking turns over as many rounds as there
+// are candidates, each round starting one candidate further on, with an
+// event between consecutive blocks.  The shader clock drifts under sustained
+// load (by up to ~15 % within milliseconds; it recovers when the device
+// idles), and timed in a fixed order the block times fell steadily with
+// their place in the round; rotated, every candidate takes every place once.
+// One untimed block per candidate first.  ms[i] is the time of candidate
+// i's nc * block steps.  With `copy` (a device buffer of the
+// handle's buffer size holding a copy of the state) the steps are plain steps
+// of that copy, with their traffic and cache reuse; without it each step
+// writes A, B and A again from the untouched state.
+template <typename T>
+hipError_t time_fd_rows(lb_sim *s, const std::vector<std::pair<int, int>> &cand, int block, std::vector<float> &ms,
+                        void *copy)
+{
+    using CT = typename Arith<T>::type;
+    const Params<CT> p = make_params<CT>(s);
+    T *g = copy ? static_cast<T *>(copy) : bufp<T>(s, 0), *a = bufp<T>(s, 1), *b = bufp<T>(s, 2);
+    T *out3 = copy ? g : a;
+    const size_t nc = cand.size(), n = nc * nc;
+    auto which = [&](size_t j) { return (j % nc + j / nc) % nc; };  // round j / nc, place j % nc
+    auto step = [&](const std::pair<int, int> &c) {
+        hipError_t e = launch_fd_stage<T>(g, nullptr, a, 1, p, nullptr, s->stream, c.first);
+        if (e == hipSuccess) e = launch_fd_stage<T>(a, g, b, 2, p, nullptr, s->stream, c.second);
+        if (e == hipSuccess) e = launch_fd_stage<T>(b, g, out3, 3, p, nullptr, s->stream, c.second);
+        return e;
+    };
+    ms.assign(nc, 0.0f);
+    std::vector<hipEvent_t> ev(n + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i <= n && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (size_t i = 0; i < nc; ++i)  // warm-up
+        for (int k = 0; k < block && e == hipSuccess; ++k) e = step(cand[i]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s->stream);
+    for (size_t j = 0; j < n && e == hipSuccess; ++j) {
+        for (int k = 0; k < block && e == hipSuccess; ++k) e = step(cand[which(j)]);
+        if (e == hipSuccess) e = hipEventRecord(ev[j + 1], s->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
+    for (size_t j = 0; j < n && e == hipSuccess; ++j) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, ev[j], ev[j + 1]);
+        ms[which(j)] += t;
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
     return e;
 }
 
@@ -930,31 +970,38 @@ int lb_autotune(lb_sim *s, int reps)
     }
     // CS vector rows: a scratch buffer for timing consecutive steps (without
     // it, the workgroup sizes are timed from the current buffer and the
-    // stores stay plain)
+    // stores stay plain); FD: a copy of the state for timing plain steps
+    // (without it, steps that leave the state in place)
     const bool cs_vec = s->cs && !s->fixed && s->Nx % (s->prec == P64 ? 2 : 4) == 0;
     void *scratch = nullptr;
-    if (cs_vec && hipMalloc(&scratch, s->buf_bytes) != hipSuccess) {
+    if ((cs_vec || !s->cs) && hipMalloc(&scratch, s->buf_bytes) != hipSuccess) {
         (void)hipGetLastError();
         scratch = nullptr;
     }
-    // the fastest of the candidates of one choice (cs_threads or the tile
-    // rows of one FD stage); the first candidate when there is no choice
-    auto pick = [&](const std::vector<int> &cand, int fd_stage, int *out) -> hipError_t {
-        if (cand.size() < 2) return hipSuccess;
-        float best = 0.0f;
-        for (size_t i = 0; i < cand.size(); ++i) {
-            float ms = 0.0f;
-            hipError_t e = with_type(s, [&](auto *tag) {
-                using T = std::remove_pointer_t<decltype(tag)>;
-                return s->cs ? time_candidate<T>(s, cand[i], false, 0, 8, reps, &ms, scratch)
-                             : time_candidate<T>(s, 0, false, fd_stage, cand[i], reps, &ms);
-            });
-            if (e != hipSuccess) return e;
-            if (i == 0 || ms < best) {
-                best = ms;
-                *out = cand[i];
+    if (scratch && !s->cs &&
+        hipMemcpyAsync(scratch, s->buf[0], s->buf_bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+        (void)hipFree(scratch);
+        return fail(LB_EDEVICE);
+    }
+    // the fastest of the CS candidates (workgroup size, store policy) timed
+    // by f(candidate, &ms).  The candidates take turns over as many rounds as
+    // there are candidates, each round starting one candidate further on, and
+    // each keeps its best time: the shader clock drifts by up to ~15 % over
+    // the tuning, and in a fixed order the times follow the place in the
+    // round; rotated, every candidate takes every place once.
+    auto pick = [&](size_t nc, auto &&f, size_t *arg) -> hipError_t {
+        std::vector<float> best(nc, 0.0f);
+        for (size_t round = 0; round < nc; ++round)
+            for (size_t j = 0; j < nc; ++j) {
+                const size_t i = (j + round) % nc;
+                float ms = 0.0f;
+                const hipError_t e = f(i, &ms);
+                if (e != hipSuccess) return e;
+                if (round == 0 || ms < best[i]) best[i] = ms;
             }
-        }
+        *arg = 0;
+        for (size_t i = 1; i < nc; ++i)
+            if (best[i] < best[*arg]) *arg = i;
         return hipSuccess;
     };
     int cs_threads = s->cs_threads, rows1 = s->fd_rows, rows_rest = s->fd_rows_rest;
@@ -962,38 +1009,60 @@ int lb_autotune(lb_sim *s, int reps)
     hipError_t e = hipSuccess;
     if (s->cs) {
         if (cs_vec) {
-            e = pick({0, 256, 512, 1024}, 0, &cs_threads);
+            const int threads[4] = {0, 256, 512, 1024};
+            size_t arg = 0;
+            e = pick(4, [&](size_t i, float *ms) {
+                return with_type(s, [&](auto *tag) {
+                    using T = std::remove_pointer_t<decltype(tag)>;
+                    return time_candidate<T>(s, threads[i], false, reps, ms, scratch);
+                });
+            }, &arg);
+            if (e == hipSuccess) cs_threads = threads[arg];
             // then the store policy at that workgroup size: non-temporal
             // stores pay only when the state is far larger than the
             // last-level cache, which the timing finds out
-            float t_plain = 0.0f, t_nt = 0.0f;
-            if (e == hipSuccess && scratch)
-                e = with_type(s, [&](auto *tag) {
-                    using T = std::remove_pointer_t<decltype(tag)>;
-                    hipError_t r = time_candidate<T>(s, cs_threads, false, 0, 8, reps, &t_plain, scratch);
-                    if (r == hipSuccess) r = time_candidate<T>(s, cs_threads, true, 0, 8, reps, &t_nt, scratch);
-                    return r;
-                });
-            if (e == hipSuccess && scratch) cs_nt = t_nt < t_plain;
+            if (e == hipSuccess && scratch) {
+                e = pick(2, [&](size_t i, float *ms) {
+                    return with_type(s, [&](auto *tag) {
+                        using T = std::remove_pointer_t<decltype(tag)>;
+                        return time_candidate<T>(s, cs_threads, i == 1, reps, ms, scratch);
+                    });
+                }, &arg);
+                if (e == hipSuccess) cs_nt = arg == 1;
+            }
         }
-    } else {
-        e = pick({8, 4}, 1, &rows1);
-        if (e == hipSuccess) e = pick({8, 4}, 2, &rows_rest);
     }
-    // FD: the stage launches (stage 1 + twice a later stage, with the tile
-    // heights just chosen) against the temporally blocked kernel with
-    // y-segments of 32, 64 and 128 rows
+    // FD: the four pairs of tile heights (first stage, later stages), timed
+    // over blocks of whole steps taking turns (blocks of at least 10 steps:
+    // two candidates may differ by 1-2 %); per step
+    float fd_step_ms = 0.0f;
+    if (!s->cs) {
+        const std::vector<std::pair<int, int>> cand = {{8, 8}, {8, 4}, {4, 8}, {4, 4}};
+        const int block = std::max(reps, 10);
+        std::vector<float> t;
+        e = with_type(s, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return time_fd_rows<T>(s, cand, block, t, scratch);
+        });
+        if (e == hipSuccess) {
+            size_t arg = 0;
+            for (size_t i = 1; i < cand.size(); ++i)
+                if (t[i] < t[arg]) arg = i;
+            rows1 = cand[arg].first;
+            rows_rest = cand[arg].second;
+            fd_step_ms = t[arg] / (float)(block * cand.size());
+        }
+    }
+    // FD: the stage launches (with the tile heights just chosen) against the
+    // temporally blocked kernel with y-segments of 32, 64 and 128 rows
     int fused = 0;
     if (e == hipSuccess && !s->cs && !s->imex && s->prec == P32 && fd_fused_supported(s->Q, s->fixed)) {
-        float t1 = 0.0f, t2 = 0.0f;
-        e = time_candidate<float>(s, 0, false, 1, rows1, reps, &t1);
-        if (e == hipSuccess) e = time_candidate<float>(s, 0, false, 2, rows_rest, reps, &t2);
-        float best = t1 + 2.0f * t2;
+        float best = fd_step_ms;  // per step
         for (int ys : {32, 64, 128}) {
             float tf = 0.0f;
             if (e == hipSuccess) e = time_fused(s, ys, reps, &tf);
-            if (e == hipSuccess && tf < best) {
-                best = tf;
+            if (e == hipSuccess && tf / (float)reps < best) {
+                best = tf / (float)reps;
                 fused = ys;
             }
         }

@@ -600,7 +600,11 @@ __device__ __forceinline__ void fd_stage_tile(const T *__restrict__ src, const T
         }
         if constexpr (kDma) __builtin_amdgcn_s_waitcnt(0);  // tile k+1 and the base values have landed
         __syncthreads();
-        if (ynz) dfy[0] = g1 - yface[wy * kTX + lx];
+        {
+            // read whatever v_ky and kept by a select, as the x-faces below
+            const CT yb = yface[wy * kTX + lx];
+            dfy[0] = ynz ? g1 - yb : CT(0);
+        }
 
         // c. node updates
         const auto ok = fd_plane(out + k * P, pbytes);

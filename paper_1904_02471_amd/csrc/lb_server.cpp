@@ -363,29 +363,36 @@ hipError_t lb_server::tune_order(int N)
         later_rows[N] = 4;
         return hipSuccess;
     }
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
-    float best = 0.0f;
-    int pick = 4;
-    for (int rows : {4, 8}) {
-        const BatchWork *w = rows == 8 ? d_fd[N].ptr : d_fd16[N].ptr;
-        const int nw = rows == 8 ? n_fd[N] : n_fd16[N];
-        if (e == hipSuccess) e = launch_fd_batch(d_slots.ptr, w, nw, N, 2, rows, d_epoch, stream);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(a, stream);
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_fd_batch(d_slots.ptr, w, nw, N, 2, rows, d_epoch, stream);
-        if (e == hipSuccess) e = hipEventRecord(b, stream);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && (rows == 4 || ms < best)) {
-            best = ms;
-            pick = rows;
-        }
+    // the two heights alternate launch by launch in the order 4 8 8 4 4 8 8 4,
+    // an event between consecutive launches, so that both run under the same
+    // shader clock (which drifts under sustained load and recovers when the
+    // device idles) and neither is always the first of a pair
+    constexpr int kReps = 4;
+    auto launch = [&](int c) {
+        const int rows = c ? 8 : 4;
+        return launch_fd_batch(d_slots.ptr, rows == 8 ? d_fd[N].ptr : d_fd16[N].ptr, rows == 8 ? n_fd[N] : n_fd16[N],
+                               N, 2, rows, d_epoch, stream);
+    };
+    hipEvent_t ev[2 * kReps + 1] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i <= 2 * kReps && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) e = launch(c);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+    auto which = [](int j) { return (j ^ (j >> 1)) & 1; };
+    for (int j = 0; j < 2 * kReps && e == hipSuccess; ++j) {
+        e = launch(which(j));
+        if (e == hipSuccess) e = hipEventRecord(ev[j + 1], stream);
     }
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-    if (e == hipSuccess) later_rows[N] = pick;
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * kReps]);
+    float t[2] = {0.0f, 0.0f};
+    for (int j = 0; j < 2 * kReps && e == hipSuccess; ++j) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[j], ev[j + 1]);
+        t[which(j)] += ms;
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e == hipSuccess) later_rows[N] = t[1] < t[0] ? 8 : 4;
     return e;
 }
 
