@@ -253,17 +253,22 @@ int lb_set_graph_steps(lb_sim *sim, int steps);
 int lb_set_rounding_seed(lb_sim *sim, unsigned seed);
 
 /* Autotuning of the launch shapes of plain steps (steps without sampling;
- * results are bitwise the same for every shape).  Times `reps` launches of
- * each candidate on the handle's own buffers, leaving the state unchanged,
- * and keeps the fastest: CS (vector row form only) workgroup sizes of 256,
- * 512 and 1024 threads against one chunk per thread, then at that size
- * plain against non-temporal stores (lb_set_cs_nontemporal); FD tiles of 64 x 32 and
- * 64 x 16 nodes, chosen separately for the first Runge-Kutta stage and for
- * the later stages (which also read the step's base state, so their kernels
- * hold more registers and LDS), then, where lb_set_fd_fused applies, the
+ * results are bitwise the same for every shape).  Times the candidates on
+ * the handle's own buffers, leaving the state unchanged, and keeps the
+ * fastest: CS (vector row form only) workgroup sizes of 256, 512 and 1024
+ * threads against one chunk per thread, then at that size plain against
+ * non-temporal stores (lb_set_cs_nontemporal), `reps` launches per timing;
+ * FD the four pairs of tile heights (64 x 32 or 64 x 16 nodes for the first
+ * Runge-Kutta stage and for the later ones, which also read the step's base
+ * state) as blocks of max(reps, 10) whole plain steps of a temporary copy of
+ * the state (one more state buffer while tuning; without it, steps that
+ * leave the state in place), then, where lb_set_fd_fused applies, the
  * three stage launches against the fused step with 32-, 64- and 128-row
- * segments.  Synchronises the stream.  LB_ESTATE before
- * lb_init, LB_EINVAL for reps outside [1, 1000].  The choice is kept in a
+ * segments, per step.  The candidates of a choice take turns in rotated
+ * order, so that a drift of the device clock during the tuning falls on
+ * each alike.  Synchronises the stream.  LB_ESTATE before lb_init,
+ * LB_EDEVICE if the state copy fails, LB_EINVAL for reps outside
+ * [1, 1000].  The choice is kept in a
  * process-wide cache keyed by device, model, storage, boundaries, grid and
  * Hermite order; a later call for a handle of the same key (any handle, any
  * thread) takes the cached shapes without timing. */
@@ -280,7 +285,7 @@ int lb_tuning_cache_size(void);
  * thread) or a multiple of 64 up to 1024; fd_rows (first FD stage) and
  * fd_rows_rest (later FD stages, the last IMEX stage included) 8 (64 x 32
  * tiles) or 4 (64 x 16).  LB_EINVAL otherwise.  Defaults of a new handle:
- * 0, 8, 4. */
+ * 0, 8, 8. */
 int lb_set_tuning(lb_sim *sim, int cs_threads, int fd_rows, int fd_rows_rest);
 
 /* FD plain steps by the temporally blocked kernel: the three Runge-Kutta

@@ -62,7 +62,7 @@ struct lb_sim {
     int cs_threads = 0;
     bool cs_nt = false;  // CS vector rows of plain steps: non-temporal stores
     int fd_rows = 8;
-    int fd_rows_rest = 4;
+    int fd_rows_rest = 8;
     // FD plain steps by the temporally blocked kernel with y-segments of this
     // many rows (0: three stage launches); FP32, periodic, Q = 3 or 4
     int fd_fused_ys = 0;
